@@ -1,0 +1,127 @@
+/*
+ * galkin: batched forward-model log-likelihood (and its gradient) of the
+ * bulge + disc(s) + halo disc-galaxy model of Rigamonti et al. 2022
+ * (arXiv 2205.06819), on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for many parameter vectors theta at once, the
+ * paper's model maps (Sec. 2.1-2.4), their Gaussian-PSF average (Sec. 3.1,
+ * PSF convolution equation) and the four-term Gaussian log-likelihood
+ * (Sec. 2.5.1, likelihood equation) against uploaded data maps.  Data are
+ * uploaded once per grid, as the paper's Appendix A prescribes; each call
+ * then evaluates a whole batch in one stream-ordered launch sequence.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Return value: GK_OK (0) on success, a negative GK_E* code otherwise;
+ *    nothing is enqueued when an argument is rejected.  last_error() gives a
+ *    message for the calling thread.  Functions never abort and never print.
+ *  - Parameter vectors (theta) are float64, row-major [B][stride], stride >= P
+ *    (P = n_params(grid)), in the sampling coordinates listed below; gradients
+ *    are with respect to these coordinates.  Rows outside the physical domain
+ *    (R <= 0, M/L <= 0, |k| > 1, i not in (0, 90) deg, c <= 0, non-finite
+ *    entries) are not errors: they give logL = -inf and a zero gradient row.
+ *  - "device" pointers are HIP device memory of the grid's device; the caller
+ *    owns them.  The library keeps no caller pointer after a call returns.
+ *  - hot-path calls (loglike_batch, loglike_grad_batch, eval_maps) are
+ *    asynchronous on the given hipStream_t (NULL = default stream): they do
+ *    not allocate, synchronise or read device memory on the host, so they
+ *    may be captured in a HIP graph.  Calls that share one grid handle must
+ *    not run concurrently (they share its workspace).
+ *
+ * Parameter layout (theta columns), components as configured in the grid:
+ *    frame              x0 [px], y0 [px], PA [deg], i [deg]
+ *    bulge (Hernquist)  log10 Mb [Msun], Rb [kpc], (M/L)b [Msun/Lsun]
+ *    disc j (1..n)      log10 Mdj [Msun], Rdj [kpc], (M/L)dj, kj
+ *    halo               log10 Mh [Msun], then c (NFW) or Rh [kpc] (Hernquist)
+ * The galaxy centre is the grid centre ((nx-1)/2, (ny-1)/2) plus (x0, y0);
+ * the position angle is counter-clockwise from +x (x = column index).
+ */
+#ifndef GALKIN_H
+#define GALKIN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GK_OK = 0,
+    GK_EINVAL = -1,   /* invalid argument (null pointer, size, descriptor)   */
+    GK_ENOMEM = -2,   /* device or host allocation failed                    */
+    GK_EHIP = -3,     /* a HIP runtime call or kernel launch failed          */
+    GK_ESTATE = -4    /* call out of order (e.g. loglike before set_data)    */
+};
+
+enum { GK_BULGE_NONE = 0, GK_BULGE_HERNQUIST = 1 };
+enum { GK_HALO_NONE = 0, GK_HALO_HERNQUIST = 1, GK_HALO_NFW = 2 };
+
+typedef struct gk_grid* gk_grid_t;   /* opaque; owns all device buffers */
+
+/* Grid and model description.  Maps are [ny][nx], x = column (fastest). */
+typedef struct {
+    int    nx, ny;         /* pixels per row / column, 1..4096                  */
+    double pixel_kpc;      /* kpc per pixel, > 0                                */
+    int    supersample;    /* s: odd, 1..15; the model is sampled on a lattice  */
+                           /* of spacing 1/s pixel (Appendix A sub-grid)        */
+    double psf_sigma_px;   /* Gaussian PSF sigma in pixels, >= 0; the average   */
+                           /* runs over lattice points within 3 sigma (Sec 3.1) */
+    int    bulge;          /* GK_BULGE_*                                        */
+    int    n_discs;        /* 0, 1 or 2 exponential discs (Sec. 2.3)            */
+    int    halo;           /* GK_HALO_*                                         */
+    double hubble_h;       /* NFW: M200 at 200 rho_crit(H0 = 100 h); e.g. 0.7   */
+} gk_grid_desc;
+
+/* Create a grid handle on the current HIP device.  Allocates every device
+ * buffer the hot-path calls need for batches of up to max_batch vectors
+ * (>= 1), so those calls never allocate.  *out receives the handle. */
+int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out);
+
+/* Release a grid handle and its device memory (synchronises the device). */
+int destroy_grid(gk_grid_t grid);
+
+/* Number of model parameters P of the grid's component set. */
+int n_params(gk_grid_t grid);
+
+/* Upload the observed maps (Sec. 2.5.1): value and err are float32
+ * [4][ny][nx] for surface brightness [Lsun/pc^2], l.o.s. velocity [km/s],
+ * l.o.s. dispersion [km/s] and M/L [Msun/Lsun]; err are 1-sigma errors.
+ * A pixel is masked in a map when its err is <= 0 or not finite, or its
+ * value is not finite.  on_device != 0 means both pointers are device
+ * memory.  The data are copied (the caller keeps ownership); this call is
+ * synchronous with respect to the given stream and may be repeated. */
+int set_data(gk_grid_t grid, const float* value, const float* err, int on_device,
+             void* hip_stream);
+
+/* logL[b] = sum over the four maps and their valid pixels of
+ *   -1/2 [ (F_m(p) - d_m(p))^2 / e_m(p)^2 + ln(2 pi e_m(p)^2) ],
+ * with F the PSF-averaged model (the model M/L map is 1 / <L/M>), for
+ * b in [0, B).  theta: device float64 [B][stride]; logL: device float64 [B].
+ * B may be 0 (nothing is enqueued); B <= max_batch. */
+int loglike_batch(gk_grid_t grid, const double* theta, int B, int stride, double* logL,
+                  void* hip_stream);
+
+/* As loglike_batch, and also grad[b][k] = d logL[b] / d theta[b][k] for
+ * k < P (columns P..stride-1 of grad are set to 0).  grad: device float64
+ * [B][stride].  The gradient is the exact derivative of the FP32 model
+ * (hand-written adjoint), accumulated in FP64. */
+int loglike_grad_batch(gk_grid_t grid, const double* theta, int B, int stride, double* logL,
+                       double* grad, void* hip_stream);
+
+/* PSF-averaged model maps at every pixel, float32 device [B][4][ny][nx]:
+ * surface brightness, l.o.s. velocity, l.o.s. dispersion and M/L
+ * (= 1 / PSF-averaged <L/M>).  Requires no data.  Rows outside the
+ * physical domain give NaN maps. */
+int eval_maps(gk_grid_t grid, const double* theta, int B, int stride, float* maps,
+              void* hip_stream);
+
+/* Launch shape used for batches of size >= batch_min (band of band_h x band_w
+ * pixels per workgroup; the autotuner sets these).  band_h, band_w >= 1. */
+int set_launch_shape(gk_grid_t grid, int batch_min, int band_h, int band_w);
+
+/* Message describing the last error returned on the calling thread. */
+const char* last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GALKIN_H */

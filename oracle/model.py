@@ -206,7 +206,9 @@ def stencil(spec: GridSpec):
     for b in range(-pad, pad + 1):
         for a in range(-pad, pad + 1):
             if a * a + b * b <= rad2:
-                taps.append((a, b, math.exp(-(a * a + b * b) / (2.0 * sig * sig))))
+                # sigma = 0 is the limit of a vanishing PSF: the single central tap
+                w = 1.0 if sig == 0.0 else math.exp(-(a * a + b * b) / (2.0 * sig * sig))
+                taps.append((a, b, w))
     W = sum(t[2] for t in taps)
     return taps, W, pad
 

@@ -1,0 +1,230 @@
+"""galkin: MI355X-native batched likelihood of the bulge + disc(s) + halo
+disc-galaxy model of Rigamonti et al. 2022 (arXiv 2205.06819).
+
+Thin Python binding of the C-ABI library ``libgalkin.so`` (declared in
+``include/galkin.h``).  The functions below carry the same names as the C
+entry points and only marshal arguments: every step of the likelihood runs
+in the HIP kernels.  PyTorch supplies device memory and streams.
+
+If the library has not been built (``python -m paper_2205_06819_amd.build``),
+importing this package raises an error: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgalkin.so")
+
+GK_OK, GK_EINVAL, GK_ENOMEM, GK_EHIP, GK_ESTATE = 0, -1, -2, -3, -4
+GK_BULGE_NONE, GK_BULGE_HERNQUIST = 0, 1
+GK_HALO_NONE, GK_HALO_HERNQUIST, GK_HALO_NFW = 0, 1, 2
+
+EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",
+           "loglike_grad_batch", "eval_maps", "set_launch_shape", "last_error")
+
+
+class GalkinError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"galkin error {code}: {msg}")
+        self.code = code
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("pixel_kpc", ctypes.c_double),
+                ("supersample", ctypes.c_int), ("psf_sigma_px", ctypes.c_double),
+                ("bulge", ctypes.c_int), ("n_discs", ctypes.c_int), ("halo", ctypes.c_int),
+                ("hubble_h", ctypes.c_double)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2205_06819_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.create_grid.argtypes = [ctypes.POINTER(GridDesc), i, ctypes.POINTER(vp)]
+    lib.destroy_grid.argtypes = [vp]
+    lib.n_params.argtypes = [vp]
+    lib.set_data.argtypes = [vp, vp, vp, i, vp]
+    lib.loglike_batch.argtypes = [vp, vp, i, i, vp, vp]
+    lib.loglike_grad_batch.argtypes = [vp, vp, i, i, vp, vp, vp]
+    lib.eval_maps.argtypes = [vp, vp, i, i, vp, vp]
+    lib.set_launch_shape.argtypes = [vp, i, i, i]
+    lib.last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "last_error":
+            getattr(lib, name).restype = i
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise GalkinError(rc, _lib.last_error().decode())
+    return rc
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def make_desc(spec) -> GridDesc:
+    """GridDesc from any object with the descriptor's attribute names."""
+    return GridDesc(int(spec.nx), int(spec.ny), float(spec.pixel_kpc), int(spec.supersample),
+                    float(spec.psf_sigma_px), int(spec.bulge), int(spec.n_discs), int(spec.halo),
+                    float(getattr(spec, "hubble_h", 0.7)))
+
+
+# --- C-ABI names -------------------------------------------------------------
+def create_grid(spec, max_batch: int) -> int:
+    desc = make_desc(spec)
+    h = ctypes.c_void_p()
+    _check(_lib.create_grid(ctypes.byref(desc), int(max_batch), ctypes.byref(h)))
+    return h.value
+
+
+def destroy_grid(handle: int) -> None:
+    _check(_lib.destroy_grid(handle))
+
+
+def n_params(handle: int) -> int:
+    return _check(_lib.n_params(handle))
+
+
+def set_data(handle: int, value, err, stream=None) -> None:
+    """value, err: [4, ny, nx] (numpy or torch); converted to float32."""
+    if isinstance(value, torch.Tensor) and value.is_cuda:
+        v = value.to(torch.float32).contiguous()
+        e = err.to(device=v.device, dtype=torch.float32).contiguous()
+        _check(_lib.set_data(handle, v.data_ptr(), e.data_ptr(), 1, _stream(stream)))
+        return
+    v = np.ascontiguousarray(np.asarray(value.cpu() if isinstance(value, torch.Tensor) else value,
+                                        dtype=np.float32))
+    e = np.ascontiguousarray(np.asarray(err.cpu() if isinstance(err, torch.Tensor) else err,
+                                        dtype=np.float32))
+    _check(_lib.set_data(handle, v.ctypes.data, e.ctypes.data, 0, _stream(stream)))
+
+
+def _theta(theta: torch.Tensor, P: int) -> torch.Tensor:
+    if not (theta.is_cuda and theta.dtype == torch.float64 and theta.dim() == 2):
+        raise ValueError("theta must be a 2-D float64 CUDA tensor [B, stride]")
+    if theta.stride(1) != 1:
+        theta = theta.contiguous()
+    if theta.shape[1] < P:
+        raise ValueError(f"theta has {theta.shape[1]} columns, the model has {P} parameters")
+    return theta
+
+
+def loglike_batch(handle: int, theta: torch.Tensor, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    theta = _theta(theta, n_params(handle))
+    B = theta.shape[0]
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=theta.device)
+    _check(_lib.loglike_batch(handle, theta.data_ptr(), B, theta.stride(0), out.data_ptr(),
+                              _stream(stream)))
+    return out
+
+
+def loglike_grad_batch(handle: int, theta: torch.Tensor, out: Optional[torch.Tensor] = None,
+                       grad: Optional[torch.Tensor] = None, stream=None
+                       ) -> Tuple[torch.Tensor, torch.Tensor]:
+    theta = _theta(theta, n_params(handle))
+    B = theta.shape[0]
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=theta.device)
+    if grad is None:
+        grad = torch.empty(B, theta.stride(0), dtype=torch.float64, device=theta.device)
+    _check(_lib.loglike_grad_batch(handle, theta.data_ptr(), B, theta.stride(0), out.data_ptr(),
+                                   grad.data_ptr(), _stream(stream)))
+    return out, grad[:, :theta.shape[1]]
+
+
+def eval_maps(handle: int, theta: torch.Tensor, ny: int, nx: int,
+              out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    theta = _theta(theta, n_params(handle))
+    B = theta.shape[0]
+    if out is None:
+        out = torch.empty(B, 4, ny, nx, dtype=torch.float32, device=theta.device)
+    _check(_lib.eval_maps(handle, theta.data_ptr(), B, theta.stride(0), out.data_ptr(),
+                          _stream(stream)))
+    return out
+
+
+def set_launch_shape(handle: int, batch_min: int, band_h: int, band_w: int) -> None:
+    _check(_lib.set_launch_shape(handle, int(batch_min), int(band_h), int(band_w)))
+
+
+def last_error() -> str:
+    return _lib.last_error().decode()
+
+
+# --- convenience wrapper -------------------------------------------------------
+class Grid:
+    """Owns one grid handle (device buffers for one galaxy's maps)."""
+
+    def __init__(self, spec, max_batch: int):
+        self.spec = spec
+        self.nx, self.ny = int(spec.nx), int(spec.ny)
+        self.handle = create_grid(spec, max_batch)
+        self.P = n_params(self.handle)
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            destroy_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_data(self, value, err, stream=None):
+        set_data(self.handle, value, err, stream)
+
+    def loglike(self, theta, out=None, stream=None):
+        return loglike_batch(self.handle, theta, out, stream)
+
+    def loglike_grad(self, theta, out=None, grad=None, stream=None):
+        return loglike_grad_batch(self.handle, theta, out, grad, stream)
+
+    def maps(self, theta, out=None, stream=None):
+        return eval_maps(self.handle, theta, self.ny, self.nx, out, stream)
+
+    def set_launch_shape(self, batch_min, band_h, band_w):
+        set_launch_shape(self.handle, batch_min, band_h, band_w)
+
+
+class LogLike(torch.autograd.Function):
+    """logL = LogLike.apply(theta, grid): float64 [B]; backward uses the
+    hand-written adjoint kernel (d logL / d theta)."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, grid: Grid):
+        if theta.requires_grad:
+            logL, g = grid.loglike_grad(theta.detach())
+            ctx.save_for_backward(g.clone())
+        else:
+            logL = grid.loglike(theta)
+        return logL
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return gout[:, None] * g, None

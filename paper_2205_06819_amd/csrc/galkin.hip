@@ -1,0 +1,709 @@
+// galkin: HIP implementation (gfx950) of the batched disc-galaxy likelihood.
+//
+// One workgroup evaluates one parameter vector (theta) on one rectangular
+// band of pixels.  It streams the band's padded fine lattice row by row:
+//
+//   model phase   every thread evaluates lattice points of the next chunk
+//                 (paper Sec. 2.1-2.4) into an LDS ring buffer;
+//   stencil phase each (pixel column, map) pair forms the horizontal partial
+//                 sums of the circular Gaussian stencil (Sec. 3.1, PSF
+//                 equation) along each completed lattice row and pushes them,
+//                 weighted by the vertical Gaussian factor, into LDS
+//                 accumulators of the pixel rows that row reaches;
+//   finalize      when the last lattice row of a pixel row is in, that row's
+//                 PSF averages are complete: residuals against the data and
+//                 the FP64 chi^2 (Sec. 2.5.1, likelihood equation).
+//
+// Only lattice points inside the union of the stencils of valid pixels are
+// evaluated.  Per-band FP64 partial chi^2 are combined in band order by the
+// last workgroup of each theta (deterministic, graph-capturable).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "galkin.h"
+#include "gk_device.h"
+
+namespace gk {
+
+enum { MODE_LOGL = 0, MODE_FBAR = 1, MODE_MAPS = 2 };
+constexpr int MAX_BANDS = 1024;       // per theta
+constexpr int RED_SLOTS = 16;         // waves per workgroup (<= 1024 threads)
+
+struct FwdArgs {
+    GridGeom geo;
+    const float* gw;        // [pad + 1] 1-D Gaussian factors exp(-a^2 / 2 (sigma s)^2)
+    const int* aof;         // [pad + 1] half-width A(|b|) of the stencil at row offset b
+    const int4* push;       // entries (d, A, weight bits, 0) per row phase, A ascending
+    const int* push_off;    // [s + 1]
+    float invW;             // 1 / sum of the 2-D stencil weights
+    int nslot;              // accumulator slots (power of two)
+    const float* val;       // data [4][ny][nx]
+    const float* ivar;      // inverse variances [4][ny][nx], 0 = masked
+    const int2* span;       // [ny] first / last column valid in any map
+    double logdet;          // sum of ln(2 pi e^2) over valid pixels
+    int band_h, band_w, nbx, nbands;
+    int ring;               // ring capacity in points (power of two)
+    int ppt;                // lattice points per thread per model phase
+    const double* theta;
+    int stride;
+    double* logL;
+    float* maps;            // MODE_MAPS output [B][4][ny][nx]
+    float* fbar;            // MODE_FBAR output [B][4][ny][nx]: d logL / d F
+    double* partials;       // [B][nbands]
+    unsigned* counters;     // [B]
+};
+
+struct Layout {             // LDS carve-up, identical on host and device
+    int tab, ring, acc, red, rows_lo, rows_start, total_bytes;
+};
+
+__host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
+
+__host__ __device__ inline Layout make_layout(int ring, int nslot, int band_w, int nfrm) {
+    Layout L;
+    int off = 0;                                   // in 4-byte words
+    L.tab = off;        off += TAB_ALL;
+    L.ring = off;       off += 4 * ring;
+    L.acc = off;        off += nslot * 4 * band_w;
+    off = (off + 3) & ~3;
+    L.red = off;        off += 2 * RED_SLOTS;      // doubles
+    L.rows_lo = off;    off += nfrm;
+    L.rows_start = off; off += nfrm + 1;
+    L.total_bytes = 4 * off;
+    return L;
+}
+
+// Block-wide exclusive scan of n ints in place (n small); returns the total.
+__device__ inline int block_exclusive_scan(int* a, int n, int* scratch /*RED_SLOTS ints*/) {
+    const int tid = threadIdx.x, BS = blockDim.x;
+    const int per = (n + BS - 1) / BS;
+    const int lo = min(n, tid * per), hi = min(n, lo + per);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += a[i];
+    // inclusive wave scan
+    const int lane = tid & 63, wave = tid >> 6;
+    int x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) scratch[wave] = x;
+    __syncthreads();
+    int wbase = 0;
+    const int nw = (BS + 63) >> 6;
+    for (int w = 0; w < wave; ++w) wbase += scratch[w];
+    int total = 0;
+    for (int w = 0; w < nw; ++w) total += scratch[w];
+    int run = wbase + x - sum;                      // exclusive prefix of this thread
+    for (int i = lo; i < hi; ++i) {
+        const int v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+template <int BULGE, int NDISC, int HALO, int MODE>
+__global__ void __launch_bounds__(1024) fwd_kernel(FwdArgs a) {
+    extern __shared__ __align__(16) float smem[];
+    const int tid = threadIdx.x, BS = blockDim.x;
+    const int band = blockIdx.x % a.nbands;
+    const int b = blockIdx.x / a.nbands;
+    const GridGeom& G = a.geo;
+    const int s = G.s, pad = G.pad, hs = G.hs;
+    const int by = band / a.nbx, bx = band - by * a.nbx;
+    const int j0 = by * a.band_h, j1 = min(G.ny, j0 + a.band_h);
+    const int c0 = bx * a.band_w, c1 = min(G.nx, c0 + a.band_w);
+    const int NR = j1 - j0, NC = c1 - c0;
+    const int NFR = (NR - 1) * s + 2 * pad + 1;
+    const int vlo = j0 * s + hs;                    // lattice row of local row 0
+    const int nfrm = nfr_max(a.band_h, s, pad);
+    const Layout L = make_layout(a.ring, a.nslot, a.band_w, nfrm);
+    float* s_tab = smem + L.tab;
+    float* s_ring = smem + L.ring;
+    float* s_acc = smem + L.acc;
+    double* s_red = (double*)(smem + L.red);
+    int* s_lo = (int*)(smem + L.rows_lo);
+    int* s_start = (int*)(smem + L.rows_start);
+    const int RMASK = a.ring - 1;
+    const int SMASK = a.nslot - 1;
+    const int BW = a.band_w;
+
+    // --- parameters of this theta (FP64 -> FP32 constants, wave-uniform)
+    const TC tc = uniform_tc(make_tc(a.theta + (size_t)b * a.stride, G));
+    if (!tc.valid) {
+        if (MODE == MODE_MAPS) {
+            const float qnan = __int_as_float(0x7fc00000);
+            for (int p = tid; p < 4 * NR * NC; p += BS) {
+                const int m = p / (NR * NC), rem = p - m * NR * NC, jj = rem / NC, c = rem - jj * NC;
+                a.maps[(size_t)b * 4 * G.ny * G.nx + ((size_t)m * G.ny + j0 + jj) * G.nx + c0 + c] = qnan;
+            }
+        } else if (band == 0 && tid == 0) {
+            a.logL[b] = -INFINITY;
+        }
+        return;
+    }
+
+    // --- prologue: tables, zeroed ring and accumulators, row spans
+    for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = gk_tab_gh[i];
+    for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
+    for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
+    for (int i = tid; i < 4 * a.ring; i += BS) s_ring[i] = 0.0f;
+    for (int i = tid; i < a.nslot * 4 * BW; i += BS) s_acc[i] = 0.0f;
+    for (int r = tid; r < NFR; r += BS) {
+        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;   // ceil((r - 2 pad) / s)
+        const int jhi = min(NR - 1, r / s);
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int jj = jlo; jj <= jhi; ++jj) {
+            int bb = r - jj * s - pad;
+            bb = bb < 0 ? -bb : bb;
+            int cl = c0, ch = c1 - 1;
+            if (MODE != MODE_MAPS) {
+                const int2 sp = a.span[j0 + jj];
+                cl = max(cl, sp.x);
+                ch = min(ch, sp.y);
+            }
+            if (cl <= ch) {
+                const int A = a.aof[bb];
+                lo = min(lo, cl * s + hs + pad - A);
+                hi = max(hi, ch * s + hs + pad + A);
+            }
+        }
+        const int w = hi >= lo ? hi - lo + 1 : 0;
+        s_lo[r] = w ? lo : 0;
+        s_start[r] = w;
+    }
+    __syncthreads();
+    const int total = block_exclusive_scan(s_start, NFR, (int*)s_red);
+    if (tid == 0) s_start[NFR] = total;
+    __syncthreads();
+
+    const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
+                 (const float4*)(s_tab + TAB_GH + TAB_PHI)};
+    const float invW = a.invW;
+    const int CH = BS * a.ppt;
+    double chi2 = 0.0;
+    int rcur = 0;              // this thread's row cursor (model phase)
+    int row_cons = 0;          // next lattice row to consume (stencil phase)
+    const size_t mapoff = (size_t)b * 4 * G.ny * G.nx;
+
+    for (int pbase = 0; row_cons < NFR; pbase += CH) {
+        // ---- model phase
+        for (int k = 0; k < a.ppt; ++k) {
+            const int q = pbase + k * BS + tid;
+            if (q < total) {
+                while (s_start[rcur + 1] <= q) ++rcur;
+                const int u = s_lo[rcur] + (q - s_start[rcur]);
+                const int v = vlo + rcur;
+                const float du = (float)(u - tc.Ui) - tc.Uf;
+                const float dv = (float)(v - tc.Vi) - tc.Vf;
+                float fB, fV, fS, fL;
+                point_model<BULGE, NDISC, HALO>(tc, T, du, dv, fB, fV, fS, fL);
+                const int slot = q & RMASK;
+                s_ring[slot] = fB;
+                s_ring[a.ring + slot] = fV;
+                s_ring[2 * a.ring + slot] = fS;
+                s_ring[3 * a.ring + slot] = fL;
+            }
+        }
+        __syncthreads();
+        const int pend = min(pbase + CH, total);
+        // ---- stencil phase: consume every lattice row completed so far
+        while (row_cons < NFR) {
+            const int r = row_cons;
+            const int rend = uni(s_start[r + 1]);
+            if (rend > pend) break;
+            const int ph = r % s, qd = r / s;
+            const int e0 = a.push_off[ph], e1 = a.push_off[ph + 1];
+            const int rs = uni(s_start[r]) - uni(s_lo[r]);
+            for (int p = tid; p < 4 * NC; p += BS) {
+                const int m = p / NC, c = p - m * NC;
+                const float* Lm = s_ring + m * a.ring;
+                const int base = rs + (c0 + c) * s + hs + pad;
+                float H = a.gw[0] * Lm[base & RMASK];
+                int acur = 0;
+                for (int e = e0; e < e1; ++e) {
+                    const int4 E = a.push[e];
+                    const int jj = qd - E.x;
+                    if (jj < 0 || jj >= NR) continue;
+                    for (; acur < E.y; ) {
+                        ++acur;
+                        H = fmaf(a.gw[acur], Lm[(base - acur) & RMASK] + Lm[(base + acur) & RMASK], H);
+                    }
+                    float* ap = s_acc + ((jj & SMASK) * 4 + m) * BW + c;
+                    *ap = fmaf(__int_as_float(E.z), H, *ap);
+                }
+            }
+            // ---- finalize a pixel row whose last lattice row this was
+            if (r >= 2 * pad && (r - 2 * pad) % s == 0) {
+                const int jj = (r - 2 * pad) / s;
+                const int j = j0 + jj;
+                for (int p = tid; p < 4 * NC; p += BS) {
+                    const int m = p / NC, c = p - m * NC;
+                    float* ap = s_acc + ((jj & SMASK) * 4 + m) * BW + c;
+                    const float F = *ap * invW;
+                    *ap = 0.0f;
+                    const size_t pix = ((size_t)m * G.ny + j) * G.nx + c0 + c;
+                    if (MODE == MODE_MAPS) {
+                        a.maps[mapoff + pix] = (m == 3) ? 1.0f / F : F;
+                    } else {
+                        const float iv = a.ivar[pix];
+                        float gbar = 0.0f;
+                        if (iv > 0.0f) {
+                            const float Fm = (m == 3) ? 1.0f / F : F;
+                            const float res = Fm - a.val[pix];
+                            chi2 += (double)res * (double)res * (double)iv;
+                            // d logL / dF: -iv res, and for M/L = 1/F: +iv res / F^2
+                            gbar = (m == 3) ? iv * res * Fm * Fm : -iv * res;
+                        }
+                        if (MODE == MODE_FBAR) a.fbar[mapoff + pix] = gbar;
+                    }
+                }
+            }
+            ++row_cons;
+        }
+        __syncthreads();
+    }
+
+    if (MODE == MODE_MAPS) return;
+    // ---- FP64 chi^2: wave sums, then waves in order, then bands in order
+    chi2 = wave_sum(chi2);
+    const int lane = tid & 63, wave = tid >> 6;
+    if (lane == 0) s_red[wave] = chi2;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (BS + 63) / 64; ++w) t += s_red[w];
+        if (a.nbands == 1) {
+            a.logL[b] = -0.5 * (t + a.logdet);
+        } else {
+            a.partials[(size_t)b * a.nbands + band] = t;
+            const unsigned ticket = __hip_atomic_fetch_add(a.counters + b, 1u, __ATOMIC_ACQ_REL,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            if (ticket == (unsigned)a.nbands - 1) {
+                double sum = 0.0;
+                for (int k = 0; k < a.nbands; ++k)
+                    sum += __hip_atomic_load(a.partials + (size_t)b * a.nbands + k, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+                a.logL[b] = -0.5 * (sum + a.logdet);
+                __hip_atomic_store(a.counters + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+}  // namespace gk
+
+// ============================================================================
+// host side
+// ============================================================================
+using namespace gk;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHECK(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) return fail(GK_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+struct LaunchRule {
+    int batch_min, band_h, band_w;
+};
+
+struct gk_grid {
+    gk_grid_desc d;
+    GridGeom geo;
+    int P = 0, K = 0, nslot = 1, max_batch = 0, device = 0;
+    float invW = 1.f;
+    double logdet = 0.0;
+    bool has_data = false;
+    // device buffers
+    float* d_gw = nullptr;
+    int* d_aof = nullptr;
+    int4* d_push = nullptr;
+    int* d_push_off = nullptr;
+    float* d_val = nullptr;
+    float* d_ivar = nullptr;
+    int2* d_span = nullptr;
+    double* d_partials = nullptr;
+    unsigned* d_counters = nullptr;
+    float* d_fbar = nullptr;
+    std::vector<LaunchRule> rules;
+};
+
+static int valid_desc(const gk_grid_desc* d) {
+    if (!d) return fail(GK_EINVAL, "desc is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nx > 4096 || d->ny > 4096)
+        return fail(GK_EINVAL, "nx, ny must be in [1, 4096] (got %d, %d)", d->nx, d->ny);
+    if (!(d->pixel_kpc > 0.0) || !std::isfinite(d->pixel_kpc))
+        return fail(GK_EINVAL, "pixel_kpc must be finite and > 0");
+    if (d->supersample < 1 || d->supersample > 15 || d->supersample % 2 == 0)
+        return fail(GK_EINVAL, "supersample must be odd and in [1, 15] (got %d)", d->supersample);
+    if (!(d->psf_sigma_px >= 0.0) || d->psf_sigma_px > 64.0)
+        return fail(GK_EINVAL, "psf_sigma_px must be in [0, 64]");
+    if (d->bulge != GK_BULGE_NONE && d->bulge != GK_BULGE_HERNQUIST)
+        return fail(GK_EINVAL, "unknown bulge kind %d", d->bulge);
+    if (d->n_discs < 0 || d->n_discs > 2) return fail(GK_EINVAL, "n_discs must be 0, 1 or 2");
+    if (d->halo < GK_HALO_NONE || d->halo > GK_HALO_NFW) return fail(GK_EINVAL, "unknown halo kind %d", d->halo);
+    if (d->halo == GK_HALO_NFW && !(d->hubble_h > 0.0)) return fail(GK_EINVAL, "hubble_h must be > 0");
+    if (d->bulge == GK_BULGE_NONE && d->n_discs == 0)
+        return fail(GK_EINVAL, "the model needs at least one luminous component");
+    return GK_OK;
+}
+
+static void free_grid(gk_grid* g) {
+    void* bufs[] = {g->d_gw, g->d_aof, g->d_push, g->d_push_off, g->d_val, g->d_ivar,
+                    g->d_span, g->d_partials, g->d_counters, g->d_fbar};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    delete g;
+}
+
+static int choose_rule(const gk_grid* g, int B, int& bh, int& bw) {
+    bh = g->d.ny;
+    bw = g->d.nx;
+    int best = -1;
+    for (const auto& r : g->rules)
+        if (r.batch_min <= B && r.batch_min > best) { best = r.batch_min; bh = r.band_h; bw = r.band_w; }
+    bh = std::min(bh, g->d.ny);
+    bw = std::min(bw, g->d.nx);
+    return GK_OK;
+}
+
+static int default_rules(gk_grid* g) {
+    // Large batches: whole rows of up to 128 pixels per workgroup.  Small
+    // batches: small square bands so that one theta spreads over many CUs.
+    const int nx = g->d.nx, ny = g->d.ny;
+    const int bw = std::min(nx, 128);
+    g->rules.clear();
+    g->rules.push_back({512, std::min(ny, std::max(8, 16384 / std::max(1, bw * g->d.supersample))), bw});
+    int side = std::max(4, (int)std::ceil(std::sqrt((double)nx * ny / 64.0)));
+    g->rules.push_back({1, std::min(ny, side), std::min(nx, side)});
+    int mid = std::max(8, (int)std::ceil(std::sqrt((double)nx * ny / 8.0)));
+    g->rules.push_back({32, std::min(ny, mid), std::min(nx, std::max(mid, 16))});
+    return GK_OK;
+}
+
+struct LaunchCfg {
+    int band_h, band_w, nbx, nbands, BS, ring, ppt, lds;
+};
+
+static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c) {
+    const int s = g->geo.s, pad = g->geo.pad;
+    c.band_h = band_h;
+    c.band_w = band_w;
+    c.nbx = (g->d.nx + band_w - 1) / band_w;
+    const int nby = (g->d.ny + band_h - 1) / band_h;
+    c.nbands = c.nbx * nby;
+    if (c.nbands > MAX_BANDS) return fail(GK_EINVAL, "launch shape gives %d bands (> %d)", c.nbands, MAX_BANDS);
+    c.BS = std::min(1024, std::max(64, (4 * band_w + 63) / 64 * 64));
+    c.ppt = 2;
+    const int maxw = band_w * s + 2 * pad + 1;
+    const int need = c.BS * c.ppt + maxw;
+    c.ring = 64;
+    while (c.ring < need) c.ring <<= 1;
+    const Layout L = make_layout(c.ring, g->nslot, band_w, nfr_max(band_h, s, pad));
+    c.lds = L.total_bytes;
+    if (c.lds > 64 * 1024) return fail(GK_EINVAL, "launch shape needs %d bytes of LDS (> 64 KiB)", c.lds);
+    return GK_OK;
+}
+
+template <int MODE>
+static hipError_t launch_fwd(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, int B, hipStream_t st) {
+    const int bulge = g->d.bulge, nd = g->d.n_discs, halo = g->d.halo;
+    if ((size_t)B * c.nbands * c.BS >= ((size_t)1 << 31)) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)(B * c.nbands)), block((unsigned)c.BS);
+#define GK_LAUNCH(BU, ND, HA)                                                                    \
+    if (bulge == BU && nd == ND && halo == HA) {                                                  \
+        hipLaunchKernelGGL((fwd_kernel<BU, ND, HA, MODE>), grid, block, c.lds, st, a);           \
+        return hipGetLastError();                                                                 \
+    }
+    GK_LAUNCH(1, 0, 0) GK_LAUNCH(1, 0, 1) GK_LAUNCH(1, 0, 2)
+    GK_LAUNCH(1, 1, 0) GK_LAUNCH(1, 1, 1) GK_LAUNCH(1, 1, 2)
+    GK_LAUNCH(1, 2, 0) GK_LAUNCH(1, 2, 1) GK_LAUNCH(1, 2, 2)
+    GK_LAUNCH(0, 1, 0) GK_LAUNCH(0, 1, 1) GK_LAUNCH(0, 1, 2)
+    GK_LAUNCH(0, 2, 0) GK_LAUNCH(0, 2, 1) GK_LAUNCH(0, 2, 2)
+#undef GK_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+static int check_call(const gk_grid* g, const double* theta, int B, int stride, const void* out) {
+    if (!g) return fail(GK_EINVAL, "grid is NULL");
+    if (B < 0 || B > g->max_batch) return fail(GK_EINVAL, "B = %d outside [0, max_batch = %d]", B, g->max_batch);
+    if (stride < g->P) return fail(GK_EINVAL, "stride %d < number of parameters %d", stride, g->P);
+    if (B > 0 && (!theta || !out)) return fail(GK_EINVAL, "NULL theta or output pointer");
+    return GK_OK;
+}
+
+static void fill_args(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, const double* theta, int stride) {
+    a.geo = g->geo;
+    a.gw = g->d_gw;
+    a.aof = g->d_aof;
+    a.push = g->d_push;
+    a.push_off = g->d_push_off;
+    a.invW = g->invW;
+    a.nslot = g->nslot;
+    a.val = g->d_val;
+    a.ivar = g->d_ivar;
+    a.span = g->d_span;
+    a.logdet = g->logdet;
+    a.band_h = c.band_h;
+    a.band_w = c.band_w;
+    a.nbx = c.nbx;
+    a.nbands = c.nbands;
+    a.ring = c.ring;
+    a.ppt = c.ppt;
+    a.theta = theta;
+    a.stride = stride;
+    a.logL = nullptr;
+    a.maps = nullptr;
+    a.fbar = nullptr;
+    a.partials = g->d_partials;
+    a.counters = g->d_counters;
+}
+
+extern "C" {
+
+const char* last_error(void) { return g_err.c_str(); }
+
+int n_params(gk_grid_t g) {
+    if (!g) return fail(GK_EINVAL, "grid is NULL");
+    return g->P;
+}
+
+int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
+    int rc = valid_desc(desc);
+    if (rc) return rc;
+    if (!out) return fail(GK_EINVAL, "out is NULL");
+    if (max_batch < 1 || max_batch > (1 << 20)) return fail(GK_EINVAL, "max_batch must be in [1, 2^20]");
+    *out = nullptr;
+    gk_grid* g = new gk_grid();
+    g->d = *desc;
+    g->max_batch = max_batch;
+    HIPCHECK(hipGetDevice(&g->device));
+    const int s = desc->supersample;
+    const double sig = desc->psf_sigma_px * s;             // stencil sigma in lattice units
+    const double rad2 = 9.0 * sig * sig;
+    const int pad = (int)std::floor(3.0 * sig);
+    g->geo.nx = desc->nx;
+    g->geo.ny = desc->ny;
+    g->geo.s = s;
+    g->geo.hs = (s - 1) / 2;
+    g->geo.pad = pad;
+    g->geo.pk = desc->pixel_kpc;
+    g->geo.pk_over_s = (float)(desc->pixel_kpc / s);
+    const double H = 0.1 * desc->hubble_h;                 // km/s/kpc
+    g->geo.rho_crit = 3.0 * H * H / (8.0 * PI * G_KPC);
+    g->geo.bulge = desc->bulge;
+    g->geo.ndisc = desc->n_discs;
+    g->geo.halo = desc->halo;
+    g->P = 4 + 3 * (desc->bulge != 0) + 4 * desc->n_discs + 2 * (desc->halo != 0);
+    // 1-D Gaussian factors (FP32) and the stencil half-widths
+    std::vector<float> gw(pad + 1);
+    std::vector<int> aof(pad + 1);
+    for (int a = 0; a <= pad; ++a) gw[a] = (float)std::exp(-(double)a * a / (2.0 * sig * sig + 1e-300));
+    if (sig == 0.0) gw[0] = 1.0f;
+    double W = 0.0;
+    int K = 0;
+    for (int bb = 0; bb <= pad; ++bb) {
+        int A = -1;
+        for (int a = 0; a <= pad; ++a)
+            if ((double)a * a + (double)bb * bb <= rad2) A = a;
+        aof[bb] = A;
+    }
+    for (int bb = -pad; bb <= pad; ++bb)
+        for (int a = -pad; a <= pad; ++a)
+            if ((double)a * a + (double)bb * bb <= rad2) {
+                W += (double)gw[std::abs(a)] * (double)gw[std::abs(bb)];
+                ++K;
+            }
+    if (K == 0) { gw[0] = 1.0f; W = 1.0; K = 1; aof[0] = 0; }
+    g->K = K;
+    g->invW = (float)(1.0 / W);
+    // push table: for lattice row phase ph = r mod s, the pixel rows jj = r/s - d
+    // with |b| = |d s + ph - pad| <= pad, sorted by A(|b|) ascending
+    std::vector<int4> push;
+    std::vector<int> push_off(s + 1, 0);
+    for (int ph = 0; ph < s; ++ph) {
+        push_off[ph] = (int)push.size();
+        std::vector<int4> ent;
+        for (int d = 0; d * s + ph <= 2 * pad; ++d) {
+            const int bb = std::abs(d * s + ph - pad);
+            const float w = gw[bb];
+            int wb;
+            std::memcpy(&wb, &w, 4);
+            ent.push_back(make_int4(d, aof[bb], wb, 0));
+        }
+        std::stable_sort(ent.begin(), ent.end(), [](const int4& x, const int4& y) { return x.y < y.y; });
+        push.insert(push.end(), ent.begin(), ent.end());
+    }
+    push_off[s] = (int)push.size();
+    int nslot = 1;
+    while (nslot < 2 * pad / s + 1) nslot <<= 1;
+    g->nslot = nslot;
+    const size_t npix = (size_t)desc->nx * desc->ny;
+#define ALLOC(ptr, bytes)                                                                \
+    if (hipMalloc((void**)&(ptr), (bytes)) != hipSuccess) {                              \
+        free_grid(g);                                                                    \
+        return fail(GK_ENOMEM, "hipMalloc of %zu bytes failed", (size_t)(bytes));       \
+    }
+    ALLOC(g->d_gw, sizeof(float) * (pad + 1));
+    ALLOC(g->d_aof, sizeof(int) * (pad + 1));
+    ALLOC(g->d_push, sizeof(int4) * push.size());
+    ALLOC(g->d_push_off, sizeof(int) * (s + 1));
+    ALLOC(g->d_val, sizeof(float) * 4 * npix);
+    ALLOC(g->d_ivar, sizeof(float) * 4 * npix);
+    ALLOC(g->d_span, sizeof(int2) * desc->ny);
+    ALLOC(g->d_partials, sizeof(double) * (size_t)max_batch * MAX_BANDS);
+    ALLOC(g->d_counters, sizeof(unsigned) * (size_t)max_batch);
+    ALLOC(g->d_fbar, sizeof(float) * 4 * npix * (size_t)max_batch);
+#undef ALLOC
+    if (hipMemcpy(g->d_gw, gw.data(), sizeof(float) * (pad + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_aof, aof.data(), sizeof(int) * (pad + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_push, push.data(), sizeof(int4) * push.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_push_off, push_off.data(), sizeof(int) * (s + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(g->d_counters, 0, sizeof(unsigned) * (size_t)max_batch) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        free_grid(g);
+        return fail(GK_EHIP, "upload of the stencil tables failed");
+    }
+    default_rules(g);
+    *out = g;
+    return GK_OK;
+}
+
+int destroy_grid(gk_grid_t g) {
+    if (!g) return fail(GK_EINVAL, "grid is NULL");
+    (void)hipDeviceSynchronize();
+    free_grid(g);
+    return GK_OK;
+}
+
+int set_launch_shape(gk_grid_t g, int batch_min, int band_h, int band_w) {
+    if (!g) return fail(GK_EINVAL, "grid is NULL");
+    if (batch_min < 1 || band_h < 1 || band_w < 1) return fail(GK_EINVAL, "batch_min, band_h, band_w must be >= 1");
+    LaunchCfg c;
+    int rc = make_cfg(g, std::min(band_h, g->d.ny), std::min(band_w, g->d.nx), c);
+    if (rc) return rc;
+    for (auto& r : g->rules)
+        if (r.batch_min == batch_min) { r.band_h = band_h; r.band_w = band_w; return GK_OK; }
+    g->rules.push_back({batch_min, band_h, band_w});
+    return GK_OK;
+}
+
+int set_data(gk_grid_t g, const float* value, const float* err, int on_device, void* stream) {
+    if (!g) return fail(GK_EINVAL, "grid is NULL");
+    if (!value || !err) return fail(GK_EINVAL, "NULL value or err");
+    const int nx = g->d.nx, ny = g->d.ny;
+    const size_t n = (size_t)4 * nx * ny;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<float> v(n), e(n);
+    if (on_device) {
+        HIPCHECK(hipMemcpyAsync(v.data(), value, n * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(e.data(), err, n * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+    } else {
+        std::memcpy(v.data(), value, n * sizeof(float));
+        std::memcpy(e.data(), err, n * sizeof(float));
+    }
+    std::vector<float> iv(n, 0.0f), dv(n, 0.0f);
+    std::vector<int2> span(ny, make_int2(1, 0));
+    double logdet = 0.0;
+    size_t nvalid = 0;
+    for (int m = 0; m < 4; ++m)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t k = ((size_t)m * ny + j) * nx + i;
+                const double ee = e[k];
+                if (std::isfinite(v[k]) && std::isfinite(ee) && ee > 0.0) {
+                    iv[k] = (float)(1.0 / (ee * ee));
+                    dv[k] = v[k];
+                    logdet += std::log(2.0 * PI * ee * ee);
+                    ++nvalid;
+                    int2& sp = span[j];
+                    if (sp.x > sp.y) sp = make_int2(i, i);
+                    else { sp.x = std::min(sp.x, i); sp.y = std::max(sp.y, i); }
+                }
+            }
+    HIPCHECK(hipMemcpyAsync(g->d_val, dv.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(g->d_ivar, iv.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(g->d_span, span.data(), ny * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    g->logdet = logdet;
+    g->has_data = true;
+    (void)nvalid;
+    return GK_OK;
+}
+
+int loglike_batch(gk_grid_t g, const double* theta, int B, int stride, double* logL, void* stream) {
+    int rc = check_call(g, theta, B, stride, logL);
+    if (rc) return rc;
+    if (!g->has_data) return fail(GK_ESTATE, "loglike_batch before set_data");
+    if (B == 0) return GK_OK;
+    int bh, bw;
+    choose_rule(g, B, bh, bw);
+    LaunchCfg c;
+    rc = make_cfg(g, bh, bw, c);
+    if (rc) return rc;
+    FwdArgs a;
+    fill_args(g, c, a, theta, stride);
+    a.logL = logL;
+    hipError_t e = launch_fwd<MODE_LOGL>(g, c, a, B, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(GK_EHIP, "forward launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
+}
+
+int eval_maps(gk_grid_t g, const double* theta, int B, int stride, float* maps, void* stream) {
+    int rc = check_call(g, theta, B, stride, maps);
+    if (rc) return rc;
+    if (B == 0) return GK_OK;
+    int bh, bw;
+    choose_rule(g, B, bh, bw);
+    LaunchCfg c;
+    rc = make_cfg(g, bh, bw, c);
+    if (rc) return rc;
+    FwdArgs a;
+    fill_args(g, c, a, theta, stride);
+    a.maps = maps;
+    hipError_t e = launch_fwd<MODE_MAPS>(g, c, a, B, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(GK_EHIP, "maps launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
+}
+
+int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, double* logL, double* grad,
+                       void* stream) {
+    int rc = check_call(g, theta, B, stride, logL);
+    if (rc) return rc;
+    if (B > 0 && !grad) return fail(GK_EINVAL, "NULL grad");
+    if (!g->has_data) return fail(GK_ESTATE, "loglike_grad_batch before set_data");
+    (void)stream;
+    return fail(GK_ESTATE, "gradient not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,350 @@
+// Device-side building blocks of the galkin kernels (gfx950 / CDNA4).
+//
+// Per-theta constants (computed in FP64, stored as FP32), the FP32
+// special functions of the model (piecewise polynomials read from LDS), and
+// the per-lattice-point model of the paper's Sec. 2.1-2.4 with its
+// reverse-mode derivative.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GK_TABLE_QUAL __constant__
+#include "gk_tables.h"
+
+namespace gk {
+
+constexpr double G_KPC = 4.300917270e-6;     // kpc (km/s)^2 / Msun
+constexpr double PI = 3.14159265358979323846;
+constexpr float S_MIN = 1.0e-6f;             // clamp of s = R / R_b at the centre
+
+// FP32 table sizes in floats (LDS copies)
+constexpr int TAB_GH = GK_GH_NPIECE * 16;
+constexpr int TAB_PHI = GK_PHI_NPIECE * 8;
+constexpr int TAB_M = GK_M_NPIECE * 8;
+constexpr int TAB_ALL = TAB_GH + TAB_PHI + TAB_M;
+
+// ---------------------------------------------------------------------------
+// per-theta constants
+// ---------------------------------------------------------------------------
+struct TC {
+    int valid;
+    int Ui, Vi;          // integer part of the model centre in lattice units
+    float Uf, Vf;        // fractional part
+    float ca, sa;        // (pixel_kpc / s) cos PA, (pixel_kpc / s) sin PA
+    float sec2i;         // 1 / cos^2 i
+    // bulge: B_b = Ab g(s), B_b sigma_b^2 = Cb h(s), v_c^2 = GMb r / (r + Rb)^2
+    float invRb, Ab, Cb, GMb, Rb, MLb;
+    // discs: B_d = Ad 2^(r nl2Rd), v_c^2 = Kd phi(r inv2Rd); v = kf cos(phi) v_int; sigma^2 = sf v_int^2
+    float nl2Rd[2], Ad[2], inv2Rd[2], Kd[2], kf[2], sf[2], MLd[2];
+    // halo: NFW v^2 = H1 m(r H0) with H0 = 1/r_s, H1 = G M200 / (r_s mu(c));
+    //       Hernquist v^2 = H1 r / (r + H0)^2 with H0 = Rh, H1 = G Mh
+    float H0, H1;
+};
+
+struct GridGeom {
+    int nx, ny, s, hs, pad;
+    float pk_over_s;
+    double pk;
+    double rho_crit;     // Msun / kpc^3
+    int bulge, ndisc, halo;
+};
+
+__device__ __forceinline__ bool gk_finite(double x) { return x == x && fabs(x) <= 1.7e308; }
+
+// theta (sampling coordinates) -> FP32 constants, all arithmetic in FP64.
+__device__ inline TC make_tc(const double* th, const GridGeom& g) {
+    TC c;
+    bool ok = true;
+    int P = 4 + 3 * (g.bulge != 0) + 4 * g.ndisc + 2 * (g.halo != 0);
+    for (int k = 0; k < P; ++k) ok = ok && gk_finite(th[k]);
+    const double x0 = th[0], y0 = th[1], pa = th[2] * (PI / 180.0), inc = th[3] * (PI / 180.0);
+    ok = ok && th[3] > 0.0 && th[3] < 90.0;
+    const double Uc = (0.5 * (g.nx - 1) + x0) * g.s + g.hs + g.pad;
+    const double Vc = (0.5 * (g.ny - 1) + y0) * g.s + g.hs + g.pad;
+    const double Uflo = floor(Uc), Vflo = floor(Vc);
+    c.Ui = ok ? (int)Uflo : 0;
+    c.Vi = ok ? (int)Vflo : 0;
+    c.Uf = (float)(Uc - Uflo);
+    c.Vf = (float)(Vc - Vflo);
+    double spa, cpa, si, ci;
+    sincos(pa, &spa, &cpa);
+    sincos(inc, &si, &ci);
+    const double pks = g.pk / g.s;
+    c.ca = (float)(pks * cpa);
+    c.sa = (float)(pks * spa);
+    c.sec2i = (float)(1.0 / (ci * ci));
+    int k = 4;
+    c.invRb = c.Ab = c.Cb = c.GMb = c.Rb = c.MLb = 0.f;
+    if (g.bulge) {
+        const double Mb = exp10(th[k]), Rb = th[k + 1], ML = th[k + 2];
+        ok = ok && Rb > 0.0 && ML > 0.0;
+        c.invRb = (float)(1.0 / Rb);
+        c.Ab = (float)(1.0e-6 * Mb / (2.0 * PI * Rb * Rb * ML));
+        c.Cb = (float)(1.0e-6 * G_KPC * Mb * Mb / (12.0 * PI * Rb * Rb * Rb * ML));
+        c.GMb = (float)(G_KPC * Mb);
+        c.Rb = (float)Rb;
+        c.MLb = (float)ML;
+        k += 3;
+    }
+    for (int j = 0; j < 2; ++j) {
+        c.nl2Rd[j] = c.Ad[j] = c.inv2Rd[j] = c.Kd[j] = c.kf[j] = c.sf[j] = c.MLd[j] = 0.f;
+        if (j < g.ndisc) {
+            const double Md = exp10(th[k]), Rd = th[k + 1], ML = th[k + 2], kk = th[k + 3];
+            ok = ok && Rd > 0.0 && ML > 0.0 && fabs(kk) <= 1.0;
+            c.nl2Rd[j] = (float)(-1.4426950408889634 / Rd);
+            c.Ad[j] = (float)(1.0e-6 * Md / (2.0 * PI * Rd * Rd * ci * ML));
+            c.inv2Rd[j] = (float)(0.5 / Rd);
+            c.Kd[j] = (float)(2.0 * G_KPC * Md / Rd);
+            c.kf[j] = (float)(-kk * si);
+            c.sf[j] = (float)((1.0 - kk * kk) / 3.0);
+            c.MLd[j] = (float)ML;
+            k += 4;
+        }
+    }
+    c.H0 = c.H1 = 0.f;
+    if (g.halo == 2) {            // NFW (M200, c)
+        const double M200 = exp10(th[k]), conc = th[k + 1];
+        ok = ok && conc > 0.0;
+        const double r200 = cbrt(3.0 * M200 / (4.0 * PI * 200.0 * g.rho_crit));
+        const double rs = r200 / conc;
+        const double muc = log1p(conc) - conc / (1.0 + conc);
+        c.H0 = (float)(1.0 / rs);
+        c.H1 = (float)(G_KPC * M200 / (rs * muc));
+    } else if (g.halo == 1) {     // Hernquist (Mh, Rh)
+        const double Mh = exp10(th[k]), Rh = th[k + 1];
+        ok = ok && Rh > 0.0;
+        c.H0 = (float)Rh;
+        c.H1 = (float)(G_KPC * Mh);
+    }
+    c.valid = ok ? 1 : 0;
+    return c;
+}
+
+__device__ __forceinline__ float uni(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Make every field wave-uniform (the compiler keeps them in SGPRs).
+__device__ __forceinline__ TC uniform_tc(const TC& a) {
+    TC c;
+    c.valid = uni(a.valid);
+    c.Ui = uni(a.Ui); c.Vi = uni(a.Vi); c.Uf = uni(a.Uf); c.Vf = uni(a.Vf);
+    c.ca = uni(a.ca); c.sa = uni(a.sa); c.sec2i = uni(a.sec2i);
+    c.invRb = uni(a.invRb); c.Ab = uni(a.Ab); c.Cb = uni(a.Cb); c.GMb = uni(a.GMb);
+    c.Rb = uni(a.Rb); c.MLb = uni(a.MLb);
+    for (int j = 0; j < 2; ++j) {
+        c.nl2Rd[j] = uni(a.nl2Rd[j]); c.Ad[j] = uni(a.Ad[j]); c.inv2Rd[j] = uni(a.inv2Rd[j]);
+        c.Kd[j] = uni(a.Kd[j]); c.kf[j] = uni(a.kf[j]); c.sf[j] = uni(a.sf[j]);
+        c.MLd[j] = uni(a.MLd[j]);
+    }
+    c.H0 = uni(a.H0); c.H1 = uni(a.H1);
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 special functions (tables in LDS)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
+
+// Piece index and local coordinate u in [-1, 1) of x in [2^elo, 2^ehi):
+// quarter-octave pieces selected by the exponent and the top two mantissa bits.
+__device__ __forceinline__ int piece(float x, int elo, float& u) {
+    const uint32_t b = __float_as_uint(x);
+    u = __uint_as_float(0x3f800000u | ((b & 0x1FFFFFu) << 2)) * 2.0f - 3.0f;
+    return (int)(b >> 21) - ((127 + elo) << 2);
+}
+// du/dx for the piece containing x: the piece has half-width 2^(e-3).
+__device__ __forceinline__ float piece_dudx(float x) {
+    const uint32_t E = (__float_as_uint(x) >> 23) & 0xFFu;
+    return __uint_as_float((257u - E) << 23);
+}
+
+__device__ __forceinline__ float horner8(const float4 a, const float4 b, float u) {
+    float p = fmaf(b.w, u, b.z);
+    p = fmaf(p, u, b.y);
+    p = fmaf(p, u, b.x);
+    p = fmaf(p, u, a.w);
+    p = fmaf(p, u, a.z);
+    p = fmaf(p, u, a.y);
+    return fmaf(p, u, a.x);
+}
+// value and derivative d/du
+__device__ __forceinline__ float horner8d(const float4 a, const float4 b, float u, float& d) {
+    float p = b.w, q = 0.f;
+    q = fmaf(q, u, p); p = fmaf(p, u, b.z);
+    q = fmaf(q, u, p); p = fmaf(p, u, b.y);
+    q = fmaf(q, u, p); p = fmaf(p, u, b.x);
+    q = fmaf(q, u, p); p = fmaf(p, u, a.w);
+    q = fmaf(q, u, p); p = fmaf(p, u, a.z);
+    q = fmaf(q, u, p); p = fmaf(p, u, a.y);
+    q = fmaf(q, u, p); p = fmaf(p, u, a.x);
+    d = q;
+    return p;
+}
+
+// Hernquist g(s), h(s) for s >= 1e-6
+__device__ __forceinline__ void eval_gh(const float4* __restrict__ T, float s, float& g, float& h) {
+    if (s < 4096.0f) {
+        float u;
+        const int k = piece(s, GK_S_ELO, u);
+        g = horner8(T[4 * k], T[4 * k + 1], u);
+        h = horner8(T[4 * k + 2], T[4 * k + 3], u);
+    } else {
+        const float w = frcp(s), w3 = w * w * w;
+        g = w3 * GK_TAIL_G(w);
+        h = w3 * w * GK_TAIL_H(w);
+    }
+}
+__device__ __forceinline__ void eval_gh_d(const float4* __restrict__ T, float s, float& g, float& h,
+                                          float& dg, float& dh) {
+    if (s < 4096.0f) {
+        float u;
+        const int k = piece(s, GK_S_ELO, u);
+        const float dudx = piece_dudx(s);
+        g = horner8d(T[4 * k], T[4 * k + 1], u, dg);
+        h = horner8d(T[4 * k + 2], T[4 * k + 3], u, dh);
+        dg *= dudx;
+        dh *= dudx;
+    } else {
+        // s^3 g = Pg(w), s^4 h = Ph(w), w = 1/s: dg/ds = -w^4 (3 Pg + w Pg'), dh/ds = -w^5 (4 Ph + w Ph')
+        const float w = frcp(s), w2 = w * w, w3 = w2 * w;
+        const float pg = GK_TAIL_G(w), ph = GK_TAIL_H(w);
+        const float e = 1.0e-3f;                           // tails are cubics; exact slope
+        const float pg1 = (GK_TAIL_G(w + e) - GK_TAIL_G(w - e)) / (2.0f * e);
+        const float ph1 = (GK_TAIL_H(w + e) - GK_TAIL_H(w - e)) / (2.0f * e);
+        g = w3 * pg;
+        h = w3 * w * ph;
+        dg = -w3 * w * (3.0f * pg + w * pg1);
+        dh = -w3 * w2 * (4.0f * ph + w * ph1);
+    }
+}
+
+// disc phi(y) = y^2 [I0 K0 - I1 K1](y)
+__device__ __forceinline__ float eval_phi(const float4* __restrict__ T, float y) {
+    if (y < 1024.0f) {
+        if (y < 5.9604645e-8f) return 0.0f;                // 2^-24: phi < 1e-13
+        float u;
+        const int k = piece(y, GK_Y_ELO, u);
+        return horner8(T[2 * k], T[2 * k + 1], u);
+    }
+    const float w = frcp(y);
+    return 0.25f * w * GK_TAIL_PHI(w);
+}
+__device__ __forceinline__ float eval_phi_d(const float4* __restrict__ T, float y, float& d) {
+    if (y < 1024.0f) {
+        if (y < 5.9604645e-8f) { d = 0.0f; return 0.0f; }
+        float u;
+        const int k = piece(y, GK_Y_ELO, u);
+        const float v = horner8d(T[2 * k], T[2 * k + 1], u, d);
+        d *= piece_dudx(y);
+        return v;
+    }
+    const float w = frcp(y);
+    const float e = 1.0e-4f;
+    const float p = GK_TAIL_PHI(w), p1 = (GK_TAIL_PHI(w + e) - GK_TAIL_PHI(w - e)) / (2.0f * e);
+    d = -0.25f * w * w * (p + w * p1);
+    return 0.25f * w * p;
+}
+
+// NFW m(x) = [ln(1+x) - x/(1+x)] / x
+__device__ __forceinline__ float eval_m(const float4* __restrict__ T, float x) {
+    if (x < 256.0f) {
+        if (x < 5.9604645e-8f) return 0.5f * x;
+        float u;
+        const int k = piece(x, GK_X_ELO, u);
+        return horner8(T[2 * k], T[2 * k + 1], u);
+    }
+    const float ix = frcp(x);
+    return (0.69314718f * flog2(1.0f + x) - x * frcp(1.0f + x)) * ix;
+}
+__device__ __forceinline__ float eval_m_d(const float4* __restrict__ T, float x, float& d) {
+    if (x < 256.0f) {
+        if (x < 5.9604645e-8f) { d = 0.5f; return 0.5f * x; }
+        float u;
+        const int k = piece(x, GK_X_ELO, u);
+        const float v = horner8d(T[2 * k], T[2 * k + 1], u, d);
+        d *= piece_dudx(x);
+        return v;
+    }
+    // m' = [x^2/(1+x)^2 - m x]... m = mu/x, mu' = x/(1+x)^2 -> m' = (mu' - m)/x
+    const float ix = frcp(x), i1 = frcp(1.0f + x);
+    const float m = (0.69314718f * flog2(1.0f + x) - x * i1) * ix;
+    d = (x * i1 * i1 - m) * ix;
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// the model at one lattice point (paper Sec. 2.1-2.4)
+// ---------------------------------------------------------------------------
+struct Tabs {
+    const float4* gh;
+    const float4* phi;
+    const float4* m;
+};
+
+// out: B_tot [Lsun/pc^2], v_los [km/s], sigma_los [km/s], <L/M> [Lsun/Msun]
+template <int BULGE, int NDISC, int HALO>
+__device__ __forceinline__ void point_model(const TC& c, const Tabs& T, float du, float dv,
+                                            float& oB, float& oV, float& oS, float& oLM) {
+    // frame: rotate by PA, deproject by i
+    const float xp = fmaf(du, c.ca, dv * c.sa);
+    const float yp = fmaf(dv, c.ca, -du * c.sa);
+    const float x2 = xp * xp, y2 = yp * yp;
+    const float r2 = fmaf(y2, c.sec2i, x2);
+    const float rinv = r2 > 0.0f ? frsq(r2) : 0.0f;
+    const float r = r2 * rinv;
+    const float cphi = xp * rinv;
+    float vc2 = 0.0f, Bt = 0.0f, BS = 0.0f, kB = 0.0f, sB = 0.0f, mass = 0.0f;
+    float scale = 1.0f;
+    if (BULGE) {
+        const float R = fsqrt(x2 + y2);
+        const float sb = fmaxf(R * c.invRb, S_MIN);
+        float g, h;
+        eval_gh(T.gh, sb, g, h);
+        const float Bb = c.Ab * g;
+        Bt = Bb;
+        BS = c.Cb * h;
+        mass = Bb * c.MLb;
+        const float q = r + c.Rb;
+        vc2 = c.GMb * r * frcp(q * q);
+    }
+    // discs: without a bulge, weights are taken relative to the largest disc
+    // exponential so that the ratios survive FP32 underflow far out
+    float ex[2];
+    float eref = 0.0f;
+    if (!BULGE && NDISC > 0) {
+        eref = r * c.nl2Rd[0];
+        if (NDISC > 1) eref = fmaxf(eref, r * c.nl2Rd[1]);
+        scale = fexp2(eref);
+    }
+#pragma unroll
+    for (int j = 0; j < NDISC; ++j) {
+        ex[j] = fexp2(fmaf(r, c.nl2Rd[j], -eref));
+        const float Bd = c.Ad[j] * ex[j];
+        Bt += Bd;
+        kB = fmaf(Bd, c.kf[j], kB);
+        sB = fmaf(Bd, c.sf[j], sB);
+        mass = fmaf(Bd, c.MLd[j], mass);
+        vc2 = fmaf(c.Kd[j], eval_phi(T.phi, r * c.inv2Rd[j]), vc2);
+    }
+    if (HALO == 2) {
+        vc2 = fmaf(c.H1, eval_m(T.m, r * c.H0), vc2);
+    } else if (HALO == 1) {
+        const float q = r + c.H0;
+        vc2 = fmaf(c.H1 * r, frcp(q * q), vc2);
+    }
+    const float vint = fsqrt(vc2);
+    const float ib = frcp(Bt);
+    oB = Bt * scale;
+    oV = cphi * vint * kB * ib;
+    oS = fsqrt(fmaf(vc2, sB, BS) * ib);
+    oLM = Bt * frcp(mass);
+}
+
+}  // namespace gk
