@@ -1,0 +1,329 @@
+"""Benchmark of the batched likelihood (and gradient) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload realistic]
+
+One step = one batched call over the whole batch of parameter vectors of the
+workload (B = 1024 for the realistic IFU cube: 80x80 pixels, 3x3 lattice per
+pixel, 2.5 px FWHM PSF, bulge + 2 discs + NFW halo, ~4000 valid spaxels).
+Inputs (parameters, data maps, errors) are resident in device memory before
+the timed region; the timed region is K back-to-back calls bracketed by HIP
+events on the stream the kernels run on.  Prints one JSON line.
+
+Also measured: gradient evaluations/s (loglike_grad_batch over the same
+batch), the plain form (the same kernels called once per parameter vector),
+the roofline position of the forward kernel, and the CPU oracle on a bounded
+sample of the same workload (worker processes on the host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector (packed FMA), vendor figure
+PEAK_FP32_NONPACKED = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+WORKLOAD_TEXT = {
+    "realistic": "realistic IFU cube: 80x80 spaxels, ~4000 valid in an elliptical mask, "
+                 "3x3 supersampling, PSF FWHM 2.5 px, bulge + inner disc + outer disc + NFW halo "
+                 "(17 params), 1024 parameter vectors",
+    "tiny": "tiny: 40x40 spaxels, no supersampling, PSF sigma 1.5 px, bulge + disc + NFW "
+            "(13 params), 64 parameter vectors",
+    "adjoint": "100x100 spaxels, 3x3 supersampling, PSF FWHM 2.5 px, 4 components (17 params), "
+               "4096 parameter vectors",
+    "stress": "300x300 spaxels, 5x5 supersampling, PSF FWHM 4 px, 4 components (17 params), "
+              "8192 parameter vectors",
+}
+
+
+# ----------------------------------------------------------------------------
+# algorithmic work of the forward pass (FP32 flops; FMA = 2, each
+# transcendental / reciprocal / square root = 1)
+# ----------------------------------------------------------------------------
+def flops_per_point(spec) -> int:
+    f = 13                                   # frame: rotate, deproject, r, cos(phi)
+    if spec.bulge:
+        f += 42                              # R, s, g and h polynomials, B, B sigma^2, mass, v_c^2
+    f += 32 * spec.n_discs                   # exp, B, light sums, phi polynomial, v_c^2
+    f += {0: 0, 1: 6, 2: 19}[spec.halo]      # Hernquist / NFW v_c^2
+    f += 13                                  # v_int, light-weighted v, sigma, <L/M>
+    return f
+
+
+def stencil_pad(spec) -> int:
+    return int(math.floor(3.0 * spec.psf_sigma_px * spec.supersample))
+
+
+def flops_per_pixel(spec) -> int:
+    """Separable circular stencil: per map, s lattice rows of incremental
+    horizontal sums (1 + 3 pad) plus (2 pad + 1) weighted pushes (2 each),
+    then the residual and FP64 chi^2 term (~5)."""
+    s, pad = spec.supersample, stencil_pad(spec)
+    return 4 * (s * (1 + 3 * pad) + 2 * (2 * pad + 1) + 5) + 1
+
+
+def needed_points(spec, mask) -> int:
+    """Lattice points inside the union of the 3-sigma stencils of valid pixels."""
+    s, pad = spec.supersample, stencil_pad(spec)
+    sig = spec.psf_sigma_px * s
+    nfy, nfx = spec.ny * s + 2 * pad, spec.nx * s + 2 * pad
+    need = np.zeros((nfy, nfx), bool)
+    jj, ii = np.nonzero(mask)
+    h = (s - 1) // 2
+    for b in range(-pad, pad + 1):
+        for a in range(-pad, pad + 1):
+            if a * a + b * b <= 9.0 * sig * sig:
+                need[jj * s + h + pad + b, ii * s + h + pad + a] = True
+    return int(need.sum())
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("galkin.hip", "gk_device.h", "gk_tables.h"):
+        p = os.path.join(ROOT, "paper_2205_06819_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+# ----------------------------------------------------------------------------
+# CPU baseline: the oracle, unchanged, on a bounded sample (worker processes)
+# ----------------------------------------------------------------------------
+def _oracle_worker(args):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    spec_d, data, err, thetas = args
+    import workloads as W
+    from oracle import model as M
+    spec = W.GridSpec(**spec_d)
+    t0 = time.perf_counter()
+    out = [M.loglike(spec, data, err, t) for t in thetas]
+    return out, time.perf_counter() - t0
+
+
+def cpu_baseline(spec, data, err, thetas, budget_s: float = 20.0):
+    import dataclasses
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                       else os.cpu_count() or 1))
+    spec_d = dataclasses.asdict(spec)
+    # calibrate on one vector in this process, then size the sample to ~budget_s of CPU work
+    sys.path.insert(0, ROOT)
+    from oracle import model as M
+    t0 = time.perf_counter()
+    M.loglike(spec, data, err, thetas[0])
+    per = time.perf_counter() - t0
+    n = int(max(cores, min(len(thetas), budget_s / max(per, 1e-4))))
+    n = (n // cores) * cores or cores
+    sample = thetas[:n]
+    chunks = [sample[i::cores] for i in range(cores)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_worker, [(spec_d, data, err, c) for c in chunks]))
+    wall = time.perf_counter() - t0
+    cpu_work = sum(r[1] for r in res)
+    vals = []
+    for i in range(n):
+        vals.append(res[i % cores][0][i // cores])
+    return {"value": n / wall, "unit": "likelihood evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} parameter vectors of the benchmark batch, {cores} worker processes, "
+                      f"{cpu_work:.1f} s of CPU work in {wall:.1f} s wall "
+                      f"({cpu_work / n * 1e3:.0f} ms per vector per core)",
+            "per_core_evals_per_s": n / cpu_work}, np.array(vals), n
+
+
+# ----------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="realistic")
+    ap.add_argument("--plain", type=int, default=256, help="number of single-vector calls timed")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(every (galaxy, parameter vector) pair is independent; see the design notes "
+              "on sharding). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_2205_06819_amd as gk
+    from paper_2205_06819_amd import autotune
+
+    wl = W.workload(args.workload)
+    spec, B = wl.spec, wl.batch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rng = np.random.default_rng(wl.seed)
+    mask = wl.mask()
+    truth = W.draw_thetas(spec, 1, rng)
+    thetas = W.draw_thetas(spec, B, rng)
+    grid = gk.Grid(spec, max_batch=B)
+    # synthetic data: the model at a seeded truth (this GPU path) plus seeded noise
+    maps = grid.maps(torch.tensor(truth, dtype=torch.float64, device=dev))[0].cpu().numpy()
+    err = W.error_maps(maps, mask)
+    data = W.noisy_data(maps, err, rng)
+    grid.set_data(data, err)
+    th = torch.tensor(thetas, dtype=torch.float64, device=dev)
+    out = torch.empty(B, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    tuned = None
+    if not args.no_tune:
+        tuned = autotune.tune(grid, th, reps=2)
+        autotune.tune(grid, th[:1], reps=20)
+        # batch sizes between 1 and B keep the default shapes
+    # ---- batched forward
+    for _ in range(args.warmup):
+        grid.loglike(th, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        grid.loglike(th, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    evals = B / (ms_step * 1e-3)
+    logl_gpu = out.cpu().numpy()
+
+    # ---- gradient
+    grad_info = {}
+    if not args.no_grad:
+        try:
+            lg, g = grid.loglike_grad(th[:1])
+            ok = True
+        except gk.GalkinError:
+            ok = False
+        if ok:
+            gbuf = torch.empty(B, th.shape[1], dtype=torch.float64, device=dev)
+            for _ in range(args.warmup):
+                grid.loglike_grad(th, out, gbuf)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                grid.loglike_grad(th, out, gbuf)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_grad = e0.elapsed_time(e1) / args.steps
+            grad_info = {"grad_evals_per_s": B / (ms_grad * 1e-3), "ms_per_grad_step": ms_grad}
+
+    # ---- plain form: one call (one launch sequence) per parameter vector
+    n_plain = min(args.plain, B)
+    one = [th[i:i + 1] for i in range(n_plain)]
+    outs = [torch.empty(1, dtype=torch.float64, device=dev) for _ in range(n_plain)]
+    for i in range(min(8, n_plain)):
+        grid.loglike(one[i], outs[i])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(n_plain):
+        grid.loglike(one[i], outs[i])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_loop_evals = n_plain / (e0.elapsed_time(e1) * 1e-3)
+    plain_vals = torch.cat(outs).cpu().numpy()
+    assert np.allclose(plain_vals, logl_gpu[:n_plain], rtol=1e-9, atol=1e-6)
+    # the same per-vector calls captured once in a HIP graph (no host overhead per call)
+    plain_graph_evals = None
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for i in range(n_plain):
+                grid.loglike(one[i], outs[i])
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for i in range(n_plain):
+                grid.loglike(one[i], outs[i])
+        graph.replay()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        reps = 3
+        for _ in range(reps):
+            graph.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_graph_evals = reps * n_plain / (e0.elapsed_time(e1) * 1e-3)
+        assert np.allclose(torch.cat(outs).cpu().numpy(), logl_gpu[:n_plain], rtol=1e-9, atol=1e-6)
+        del graph
+    except Exception as exc:  # report, do not hide
+        print(f"plain-graph timing skipped: {exc}", file=sys.stderr)
+    plain_evals = max(plain_loop_evals, plain_graph_evals or 0.0)
+
+    # ---- roofline of the forward kernel (one launch per step)
+    n_need = needed_points(spec, mask)
+    n_valid = int(mask.sum())
+    flop_theta = n_need * flops_per_point(spec) + n_valid * flops_per_pixel(spec)
+    achieved = flop_theta * B / (ms_step * 1e-3) / 1e12
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    if os.path.exists(tpath):
+        try:
+            t = json.load(open(tpath))
+            if t.get("source_hash") == source_hash():
+                traffic = t.get("bytes_per_launch")
+        except (OSError, ValueError):
+            pass
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+            "frac_of_nonpacked_fp32": round(achieved / PEAK_FP32_NONPACKED, 4),
+            "kernel": "gk::fwd_kernel<1,2,2,0>" if args.workload != "tiny" else "gk::fwd_kernel<1,1,2,0>",
+            "flop_per_vector": flop_theta,
+            "per_unit": {"lattice_points": n_need, "flop_per_point": flops_per_point(spec),
+                         "valid_spaxels": n_valid, "flop_per_spaxel": flops_per_pixel(spec)}}
+
+    # ---- CPU baseline (oracle, unchanged)
+    cpu = None
+    if not args.no_cpu:
+        cpu, cvals, n = cpu_baseline(spec, data.astype(np.float32).astype(np.float64),
+                                     err.astype(np.float32).astype(np.float64), thetas,
+                                     args.cpu_budget)
+        rel = np.abs(cvals - logl_gpu[:n]) / np.maximum(1.0, np.abs(cvals))
+        cpu["max_rel_diff_vs_gpu"] = float(rel.max())
+
+    P = spec.n_params
+    spax = spec.nx * spec.ny
+    line = {
+        "metric": "likelihood evals/s and gradient evals/s (params×spaxels/s), batched vs plain",
+        "value": round(evals, 1),
+        "unit": "likelihood evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "batch": B,
+                   "spaxels": spax, "valid_spaxels": n_valid, "params": P,
+                   "supersample": spec.supersample, "psf_sigma_px": round(spec.psf_sigma_px, 5),
+                   "launch_shape": list(tuned[:2]) if tuned else None},
+        "params_x_spaxels_per_s": round(evals * P * spax, 1),
+        "plain_evals_per_s": round(plain_evals, 1),
+        "plain_host_loop_evals_per_s": round(plain_loop_evals, 1),
+        "plain_graph_evals_per_s": round(plain_graph_evals, 1) if plain_graph_evals else None,
+        "speedup_vs_plain": round(evals / plain_evals, 2),
+        **{k: round(v, 4) for k, v in grad_info.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if "grad_evals_per_s" in grad_info:
+        line["grad_params_x_spaxels_per_s"] = round(grad_info["grad_evals_per_s"] * P * spax, 1)
+    print(json.dumps(line), flush=True)
+    grid.close()
+
+
+if __name__ == "__main__":
+    main()

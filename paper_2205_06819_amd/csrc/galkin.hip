@@ -38,19 +38,20 @@ constexpr int RED_SLOTS = 16;         // waves per workgroup (<= 1024 threads)
 
 struct FwdArgs {
     GridGeom geo;
-    const float* gw;        // [pad + 1] 1-D Gaussian factors exp(-a^2 / 2 (sigma s)^2)
+    const float* gw;        // [64] 1-D Gaussian factors exp(-a^2 / 2 (sigma s)^2), zero beyond pad
     const int* aof;         // [pad + 1] half-width A(|b|) of the stencil at row offset b
-    const int4* push;       // entries (d, A, weight bits, 0) per row phase, A ascending
-    const int* push_off;    // [s + 1]
+    const int2* tab;        // [s][DSTRIDE] (A(|b|), weight bits g(|b|)) for lattice-row phase ph and
+                            // pixel-row lag d, b = d s + ph - pad; (0, 0) where |b| > pad
     float invW;             // 1 / sum of the 2-D stencil weights
-    int nslot;              // accumulator slots (power of two)
+    int D;                  // floor(2 pad / s): lag at which a pixel row is complete
     const float* val;       // data [4][ny][nx]
     const float* ivar;      // inverse variances [4][ny][nx], 0 = masked
     const int2* span;       // [ny] first / last column valid in any map
     double logdet;          // sum of ln(2 pi e^2) over valid pixels
     int band_h, band_w, nbx, nbands;
-    int ring;               // ring capacity in points (power of two)
-    int ppt;                // lattice points per thread per model phase
+    int gsub;               // pixel-row steps per model phase (gsub * s <= RS_CAP lattice rows)
+    int xw;                 // row stride of the row buffer (floats)
+    int tpad;               // compile-time tap count used by the stencil (>= pad)
     const double* theta;
     int stride;
     double* logL;
@@ -60,22 +61,26 @@ struct FwdArgs {
     unsigned* counters;     // [B]
 };
 
-struct Layout {             // LDS carve-up, identical on host and device
-    int tab, ring, acc, red, rows_lo, rows_start, total_bytes;
+constexpr int DMAX = 10;        // largest lag D = floor(2 pad / s) supported
+constexpr int DSTRIDE = DMAX + 1;
+constexpr int RS_CAP = 16;      // lattice rows per model phase
+constexpr int GSUB_CAP = 4;     // pixel-row steps per model phase
+
+struct Layout {                 // LDS carve-up, identical on host and device
+    int tab, rows, red, rows_lo, rows_start, total_bytes;
 };
 
 __host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
 
-__host__ __device__ inline Layout make_layout(int ring, int nslot, int band_w, int nfrm) {
+__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm) {
     Layout L;
     int off = 0;                                   // in 4-byte words
     L.tab = off;        off += TAB_ALL;
-    L.ring = off;       off += 4 * ring;
-    L.acc = off;        off += nslot * 4 * band_w;
+    L.rows = off;       off += rows * 4 * xw;
     off = (off + 3) & ~3;
     L.red = off;        off += 2 * RED_SLOTS;      // doubles
     L.rows_lo = off;    off += nfrm;
-    L.rows_start = off; off += nfrm + 1;
+    L.rows_start = off; off += nfrm + 1 + RS_CAP;  // padded: phase lookups read ahead
     L.total_bytes = 4 * off;
     return L;
 }
@@ -87,7 +92,6 @@ __device__ inline int block_exclusive_scan(int* a, int n, int* scratch /*RED_SLO
     const int lo = min(n, tid * per), hi = min(n, lo + per);
     int sum = 0;
     for (int i = lo; i < hi; ++i) sum += a[i];
-    // inclusive wave scan
     const int lane = tid & 63, wave = tid >> 6;
     int x = sum;
 #pragma unroll
@@ -118,8 +122,43 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// One pixel-row step of the separable stencil for one (map, pixel column).
+// The step's s lattice rows (phases) each give horizontal partial sums
+// H_0..H_PAD at the pixel centre from one batch of LDS loads; the pixel row
+// at lag d (d steps back) takes weight g(|b|) times H_A(|b|), b = d s + ph - pad.
+// acc[d] holds the running PSF sum of the pixel row d steps back; it is
+// shifted by one each step, so acc[D] is complete after this call.
+template <int PAD>
+__device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rstride, int s, int D,
+                                            const float* __restrict__ gw, const int2* __restrict__ tab,
+                                            float (&acc)[DMAX + 1]) {
+    float g[PAD + 1];
+#pragma unroll
+    for (int k = 0; k <= PAD; ++k) g[k] = gw[k];
+    float con[DMAX + 1];
+#pragma unroll
+    for (int d = 0; d <= DMAX; ++d) con[d] = 0.0f;
+    for (int ph = 0; ph < s; ++ph) {
+        const float* L = L0 + ph * rstride;
+        float H[PAD + 1];
+        H[0] = g[0] * L[0];
+#pragma unroll
+        for (int k = 1; k <= PAD; ++k) H[k] = fmaf(g[k], L[-k] + L[k], H[k - 1]);
+        const int2* t = tab + ph * DSTRIDE;
+#pragma unroll
+        for (int d = 0; d <= DMAX; ++d) {
+            if (d > D) break;
+            const int2 e = t[d];
+            con[d] = fmaf(__int_as_float(e.y), H[e.x], con[d]);
+        }
+    }
+#pragma unroll
+    for (int d = DMAX; d >= 1; --d) acc[d] = acc[d - 1] + con[d];
+    acc[0] = con[0];
+}
+
 template <int BULGE, int NDISC, int HALO, int MODE>
-__global__ void __launch_bounds__(1024) fwd_kernel(FwdArgs a) {
+__global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
     extern __shared__ __align__(16) float smem[];
     const int tid = threadIdx.x, BS = blockDim.x;
     const int band = blockIdx.x % a.nbands;
@@ -132,17 +171,17 @@ __global__ void __launch_bounds__(1024) fwd_kernel(FwdArgs a) {
     const int NR = j1 - j0, NC = c1 - c0;
     const int NFR = (NR - 1) * s + 2 * pad + 1;
     const int vlo = j0 * s + hs;                    // lattice row of local row 0
+    const int ubase = c0 * s + hs;                  // lattice column of local column 0
     const int nfrm = nfr_max(a.band_h, s, pad);
-    const Layout L = make_layout(a.ring, a.nslot, a.band_w, nfrm);
+    const int RS = a.gsub * s;
+    const Layout L = make_layout(RS, a.xw, nfrm);
     float* s_tab = smem + L.tab;
-    float* s_ring = smem + L.ring;
-    float* s_acc = smem + L.acc;
+    float* s_rows = smem + L.rows;
     double* s_red = (double*)(smem + L.red);
     int* s_lo = (int*)(smem + L.rows_lo);
     int* s_start = (int*)(smem + L.rows_start);
-    const int RMASK = a.ring - 1;
-    const int SMASK = a.nslot - 1;
-    const int BW = a.band_w;
+    const int XW = a.xw;
+    const int D = a.D;
 
     // --- parameters of this theta (FP64 -> FP32 constants, wave-uniform)
     const TC tc = uniform_tc(make_tc(a.theta + (size_t)b * a.stride, G));
@@ -159,12 +198,11 @@ __global__ void __launch_bounds__(1024) fwd_kernel(FwdArgs a) {
         return;
     }
 
-    // --- prologue: tables, zeroed ring and accumulators, row spans
+    // --- prologue: tables, zeroed row buffer, row spans
     for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = gk_tab_gh[i];
     for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
     for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
-    for (int i = tid; i < 4 * a.ring; i += BS) s_ring[i] = 0.0f;
-    for (int i = tid; i < a.nslot * 4 * BW; i += BS) s_acc[i] = 0.0f;
+    for (int i = tid; i < RS * 4 * XW; i += BS) s_rows[i] = 0.0f;
     for (int r = tid; r < NFR; r += BS) {
         const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;   // ceil((r - 2 pad) / s)
         const int jhi = min(NR - 1, r / s);
@@ -185,97 +223,118 @@ __global__ void __launch_bounds__(1024) fwd_kernel(FwdArgs a) {
             }
         }
         const int w = hi >= lo ? hi - lo + 1 : 0;
-        s_lo[r] = w ? lo : 0;
+        s_lo[r] = w ? lo - ubase : 0;               // local column of the first needed point
         s_start[r] = w;
     }
     __syncthreads();
     const int total = block_exclusive_scan(s_start, NFR, (int*)s_red);
-    if (tid == 0) s_start[NFR] = total;
+    if (tid == 0)
+        for (int k = 0; k <= RS_CAP; ++k) s_start[NFR + k] = total;
     __syncthreads();
 
     const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
                  (const float4*)(s_tab + TAB_GH + TAB_PHI)};
     const float invW = a.invW;
-    const int CH = BS * a.ppt;
     double chi2 = 0.0;
-    int rcur = 0;              // this thread's row cursor (model phase)
-    int row_cons = 0;          // next lattice row to consume (stencil phase)
     const size_t mapoff = (size_t)b * 4 * G.ny * G.nx;
+    // one (map, pixel column) pair per thread: blockDim >= 4 * band_w
+    const int pm = tid / NC, pc = tid - (tid / NC) * NC;
+    const bool pact = tid < 4 * NC;
+    float acc[DMAX + 1];
+#pragma unroll
+    for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0f;
+    const int Q = NR + D;                           // pixel-row steps
 
-    for (int pbase = 0; row_cons < NFR; pbase += CH) {
-        // ---- model phase
-        for (int k = 0; k < a.ppt; ++k) {
-            const int q = pbase + k * BS + tid;
-            if (q < total) {
-                while (s_start[rcur + 1] <= q) ++rcur;
-                const int u = s_lo[rcur] + (q - s_start[rcur]);
-                const int v = vlo + rcur;
-                const float du = (float)(u - tc.Ui) - tc.Uf;
-                const float dv = (float)(v - tc.Vi) - tc.Vf;
-                float fB, fV, fS, fL;
-                point_model<BULGE, NDISC, HALO>(tc, T, du, dv, fB, fV, fS, fL);
-                const int slot = q & RMASK;
-                s_ring[slot] = fB;
-                s_ring[a.ring + slot] = fV;
-                s_ring[2 * a.ring + slot] = fS;
-                s_ring[3 * a.ring + slot] = fL;
+    for (int q0 = 0; q0 < Q; q0 += a.gsub) {
+        // ---- lattice rows [rA, rA + nrow) of this phase and their flat point ranges
+        const int rA = q0 * s;
+        const int nrow = max(0, min(RS, NFR - rA));
+        const int qA = uni(s_start[min(rA, NFR)]);
+        int st[RS_CAP + 1];
+        st[0] = 0;
+#pragma unroll
+        for (int k = 1; k <= RS_CAP; ++k)
+            st[k] = (k <= nrow) ? uni(s_start[rA + k]) - qA : (1 << 30);
+        int npts = 0;
+#pragma unroll
+        for (int k = 1; k <= RS_CAP; ++k) npts = (k == nrow) ? st[k] : npts;
+        // ---- data of the pixel rows completed in this phase (prefetched)
+        float pv[GSUB_CAP], pi[GSUB_CAP];
+        if (MODE != MODE_MAPS && pact) {
+#pragma unroll
+            for (int k = 0; k < GSUB_CAP; ++k) {
+                if (k >= a.gsub) break;
+                const int jj = q0 + k - D;
+                const bool ok = jj >= 0 && jj < NR;
+                const size_t pix = ((size_t)pm * G.ny + j0 + (ok ? jj : 0)) * G.nx + c0 + pc;
+                pv[k] = ok ? a.val[pix] : 0.0f;
+                pi[k] = ok ? a.ivar[pix] : 0.0f;
             }
         }
-        __syncthreads();
-        const int pend = min(pbase + CH, total);
-        // ---- stencil phase: consume every lattice row completed so far
-        while (row_cons < NFR) {
-            const int r = row_cons;
-            const int rend = uni(s_start[r + 1]);
-            if (rend > pend) break;
-            const int ph = r % s, qd = r / s;
-            const int e0 = a.push_off[ph], e1 = a.push_off[ph + 1];
-            const int rs = uni(s_start[r]) - uni(s_lo[r]);
-            for (int p = tid; p < 4 * NC; p += BS) {
-                const int m = p / NC, c = p - m * NC;
-                const float* Lm = s_ring + m * a.ring;
-                const int base = rs + (c0 + c) * s + hs + pad;
-                float H = a.gw[0] * Lm[base & RMASK];
-                int acur = 0;
-                for (int e = e0; e < e1; ++e) {
-                    const int4 E = a.push[e];
-                    const int jj = qd - E.x;
-                    if (jj < 0 || jj >= NR) continue;
-                    for (; acur < E.y; ) {
-                        ++acur;
-                        H = fmaf(a.gw[acur], Lm[(base - acur) & RMASK] + Lm[(base + acur) & RMASK], H);
-                    }
-                    float* ap = s_acc + ((jj & SMASK) * 4 + m) * BW + c;
-                    *ap = fmaf(__int_as_float(E.z), H, *ap);
-                }
+        // ---- model phase: the phase's lattice points, flat over its rows
+        for (int q = tid; q < npts; q += BS) {
+            int lr = 0, rowq = 0;
+#pragma unroll
+            for (int k = 1; k < RS_CAP; ++k) {
+                if (k >= nrow) break;
+                const bool ge = q >= st[k];
+                lr += ge ? 1 : 0;
+                rowq = ge ? st[k] : rowq;
             }
-            // ---- finalize a pixel row whose last lattice row this was
-            if (r >= 2 * pad && (r - 2 * pad) % s == 0) {
-                const int jj = (r - 2 * pad) / s;
-                const int j = j0 + jj;
-                for (int p = tid; p < 4 * NC; p += BS) {
-                    const int m = p / NC, c = p - m * NC;
-                    float* ap = s_acc + ((jj & SMASK) * 4 + m) * BW + c;
-                    const float F = *ap * invW;
-                    *ap = 0.0f;
-                    const size_t pix = ((size_t)m * G.ny + j) * G.nx + c0 + c;
+            const int r = rA + lr;
+            const int x = s_lo[r] + (q - rowq);                 // local column
+            const int u = ubase + x;
+            const int v = vlo + r;
+            const float du = (float)(u - tc.Ui) - tc.Uf;
+            const float dv = (float)(v - tc.Vi) - tc.Vf;
+            float fB, fV, fS, fL;
+            point_model<BULGE, NDISC, HALO>(tc, T, du, dv, fB, fV, fS, fL);
+            float* row = s_rows + lr * 4 * XW + x;
+            row[0] = fB;
+            row[XW] = fV;
+            row[2 * XW] = fS;
+            row[3 * XW] = fL;
+        }
+        __syncthreads();
+        // ---- stencil phase: per (map, column) pair, in registers
+        if (pact) {
+#pragma unroll
+            for (int k = 0; k < GSUB_CAP; ++k) {
+                if (k >= a.gsub) break;
+                const int q = q0 + k;
+                if (q >= Q) break;
+                const float* L0 = s_rows + (k * s) * 4 * XW + pm * XW + pc * s + pad;
+#define GK_SUB(PADV) stencil_sub<PADV>(L0, 4 * XW, s, D, a.gw, a.tab, acc)
+                switch (a.tpad) {
+                    case 4: GK_SUB(4); break;
+                    case 6: GK_SUB(6); break;
+                    case 9: GK_SUB(9); break;
+                    case 12: GK_SUB(12); break;
+                    case 16: GK_SUB(16); break;
+                    case 20: GK_SUB(20); break;
+                    default: GK_SUB(25); break;
+                }
+#undef GK_SUB
+                const int jj = q - D;                   // pixel row completed by this step
+                if (jj >= 0) {
+                    const float F = acc[D] * invW;
+                    const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
                     if (MODE == MODE_MAPS) {
-                        a.maps[mapoff + pix] = (m == 3) ? 1.0f / F : F;
+                        a.maps[mapoff + pix] = (pm == 3) ? 1.0f / F : F;
                     } else {
-                        const float iv = a.ivar[pix];
+                        const float iv = pi[k];
                         float gbar = 0.0f;
                         if (iv > 0.0f) {
-                            const float Fm = (m == 3) ? 1.0f / F : F;
-                            const float res = Fm - a.val[pix];
+                            const float Fm = (pm == 3) ? 1.0f / F : F;
+                            const float res = Fm - pv[k];
                             chi2 += (double)res * (double)res * (double)iv;
                             // d logL / dF: -iv res, and for M/L = 1/F: +iv res / F^2
-                            gbar = (m == 3) ? iv * res * Fm * Fm : -iv * res;
+                            gbar = (pm == 3) ? iv * res * Fm * Fm : -iv * res;
                         }
                         if (MODE == MODE_FBAR) a.fbar[mapoff + pix] = gbar;
                     }
                 }
             }
-            ++row_cons;
         }
         __syncthreads();
     }
@@ -339,15 +398,14 @@ struct LaunchRule {
 struct gk_grid {
     gk_grid_desc d;
     GridGeom geo;
-    int P = 0, K = 0, nslot = 1, max_batch = 0, device = 0;
+    int P = 0, K = 0, D = 0, max_batch = 0, device = 0, tpad = 0;
     float invW = 1.f;
     double logdet = 0.0;
     bool has_data = false;
     // device buffers
     float* d_gw = nullptr;
     int* d_aof = nullptr;
-    int4* d_push = nullptr;
-    int* d_push_off = nullptr;
+    int2* d_tab = nullptr;
     float* d_val = nullptr;
     float* d_ivar = nullptr;
     int2* d_span = nullptr;
@@ -378,7 +436,7 @@ static int valid_desc(const gk_grid_desc* d) {
 }
 
 static void free_grid(gk_grid* g) {
-    void* bufs[] = {g->d_gw, g->d_aof, g->d_push, g->d_push_off, g->d_val, g->d_ivar,
+    void* bufs[] = {g->d_gw, g->d_aof, g->d_tab, g->d_val, g->d_ivar,
                     g->d_span, g->d_partials, g->d_counters, g->d_fbar};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
@@ -397,12 +455,12 @@ static int choose_rule(const gk_grid* g, int B, int& bh, int& bw) {
 }
 
 static int default_rules(gk_grid* g) {
-    // Large batches: whole rows of up to 128 pixels per workgroup.  Small
+    // Large batches: whole frames (up to 128 pixels wide) per workgroup.  Small
     // batches: small square bands so that one theta spreads over many CUs.
     const int nx = g->d.nx, ny = g->d.ny;
     const int bw = std::min(nx, 128);
     g->rules.clear();
-    g->rules.push_back({512, std::min(ny, std::max(8, 16384 / std::max(1, bw * g->d.supersample))), bw});
+    g->rules.push_back({512, ny, bw});
     int side = std::max(4, (int)std::ceil(std::sqrt((double)nx * ny / 64.0)));
     g->rules.push_back({1, std::min(ny, side), std::min(nx, side)});
     int mid = std::max(8, (int)std::ceil(std::sqrt((double)nx * ny / 8.0)));
@@ -411,7 +469,7 @@ static int default_rules(gk_grid* g) {
 }
 
 struct LaunchCfg {
-    int band_h, band_w, nbx, nbands, BS, ring, ppt, lds;
+    int band_h, band_w, nbx, nbands, BS, gsub, xw, lds;
 };
 
 static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c) {
@@ -422,14 +480,17 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c) {
     const int nby = (g->d.ny + band_h - 1) / band_h;
     c.nbands = c.nbx * nby;
     if (c.nbands > MAX_BANDS) return fail(GK_EINVAL, "launch shape gives %d bands (> %d)", c.nbands, MAX_BANDS);
-    c.BS = std::min(1024, std::max(64, (4 * band_w + 63) / 64 * 64));
-    c.ppt = 2;
-    const int maxw = band_w * s + 2 * pad + 1;
-    const int need = c.BS * c.ppt + maxw;
-    c.ring = 64;
-    while (c.ring < need) c.ring <<= 1;
-    const Layout L = make_layout(c.ring, g->nslot, band_w, nfr_max(band_h, s, pad));
-    c.lds = L.total_bytes;
+    if (band_w > 128) return fail(GK_EINVAL, "band_w %d > 128", band_w);
+    c.BS = std::min(512, std::max(64, (4 * band_w + 63) / 64 * 64));
+    c.xw = band_w * s + 2 * pad + 1;
+    // pixel-row steps per model phase: about four lattice points per thread,
+    // at most RS_CAP lattice rows, and the row buffer within ~40 KiB of LDS
+    const int nfrm = nfr_max(band_h, s, pad);
+    int gs = std::max(1, (4 * c.BS) / std::max(1, s * c.xw));
+    gs = std::min({gs, GSUB_CAP, std::max(1, RS_CAP / s)});
+    while (gs > 1 && make_layout(gs * s, c.xw, nfrm).total_bytes > 40 * 1024) --gs;
+    c.gsub = gs;
+    c.lds = make_layout(gs * s, c.xw, nfrm).total_bytes;
     if (c.lds > 64 * 1024) return fail(GK_EINVAL, "launch shape needs %d bytes of LDS (> 64 KiB)", c.lds);
     return GK_OK;
 }
@@ -465,10 +526,9 @@ static void fill_args(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, const do
     a.geo = g->geo;
     a.gw = g->d_gw;
     a.aof = g->d_aof;
-    a.push = g->d_push;
-    a.push_off = g->d_push_off;
+    a.tab = g->d_tab;
     a.invW = g->invW;
-    a.nslot = g->nslot;
+    a.D = g->D;
     a.val = g->d_val;
     a.ivar = g->d_ivar;
     a.span = g->d_span;
@@ -477,8 +537,9 @@ static void fill_args(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, const do
     a.band_w = c.band_w;
     a.nbx = c.nbx;
     a.nbands = c.nbands;
-    a.ring = c.ring;
-    a.ppt = c.ppt;
+    a.gsub = c.gsub;
+    a.xw = c.xw;
+    a.tpad = g->tpad;
     a.theta = theta;
     a.stride = stride;
     a.logL = nullptr;
@@ -546,37 +607,35 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
     if (K == 0) { gw[0] = 1.0f; W = 1.0; K = 1; aof[0] = 0; }
     g->K = K;
     g->invW = (float)(1.0 / W);
-    // push table: for lattice row phase ph = r mod s, the pixel rows jj = r/s - d
-    // with |b| = |d s + ph - pad| <= pad, sorted by A(|b|) ascending
-    std::vector<int4> push;
-    std::vector<int> push_off(s + 1, 0);
-    for (int ph = 0; ph < s; ++ph) {
-        push_off[ph] = (int)push.size();
-        std::vector<int4> ent;
-        for (int d = 0; d * s + ph <= 2 * pad; ++d) {
-            const int bb = std::abs(d * s + ph - pad);
-            const float w = gw[bb];
-            int wb;
-            std::memcpy(&wb, &w, 4);
-            ent.push_back(make_int4(d, aof[bb], wb, 0));
-        }
-        std::stable_sort(ent.begin(), ent.end(), [](const int4& x, const int4& y) { return x.y < y.y; });
-        push.insert(push.end(), ent.begin(), ent.end());
+    // lag table: lattice row of phase ph (= row mod s) reaches the pixel row
+    // d steps back with b = d s + ph - pad; weight g(|b|), half-width A(|b|)
+    const int D = 2 * pad / s;
+    if (pad > 25 || D > DMAX) {
+        delete g;
+        return fail(GK_EINVAL, "PSF too wide for this build: 3 sigma s = %d lattice points (max 25) and "
+                               "2 pad / s = %d (max %d)", pad, D, DMAX);
     }
-    push_off[s] = (int)push.size();
-    int nslot = 1;
-    while (nslot < 2 * pad / s + 1) nslot <<= 1;
-    g->nslot = nslot;
+    g->D = D;
+    std::vector<int2> tab((size_t)s * DSTRIDE, make_int2(0, 0));
+    for (int ph = 0; ph < s; ++ph)
+        for (int d = 0; d <= D; ++d) {
+            const int bb = d * s + ph - pad;
+            if (std::abs(bb) <= pad) {
+                const float w = gw[std::abs(bb)];
+                int wb;
+                std::memcpy(&wb, &w, 4);
+                tab[(size_t)ph * DSTRIDE + d] = make_int2(aof[std::abs(bb)], wb);
+            }
+        }
     const size_t npix = (size_t)desc->nx * desc->ny;
 #define ALLOC(ptr, bytes)                                                                \
     if (hipMalloc((void**)&(ptr), (bytes)) != hipSuccess) {                              \
         free_grid(g);                                                                    \
         return fail(GK_ENOMEM, "hipMalloc of %zu bytes failed", (size_t)(bytes));       \
     }
-    ALLOC(g->d_gw, sizeof(float) * (pad + 1));
+    ALLOC(g->d_gw, sizeof(float) * std::max(pad + 1, 64));
     ALLOC(g->d_aof, sizeof(int) * (pad + 1));
-    ALLOC(g->d_push, sizeof(int4) * push.size());
-    ALLOC(g->d_push_off, sizeof(int) * (s + 1));
+    ALLOC(g->d_tab, sizeof(int2) * tab.size());
     ALLOC(g->d_val, sizeof(float) * 4 * npix);
     ALLOC(g->d_ivar, sizeof(float) * 4 * npix);
     ALLOC(g->d_span, sizeof(int2) * desc->ny);
@@ -584,10 +643,19 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
     ALLOC(g->d_counters, sizeof(unsigned) * (size_t)max_batch);
     ALLOC(g->d_fbar, sizeof(float) * 4 * npix * (size_t)max_batch);
 #undef ALLOC
-    if (hipMemcpy(g->d_gw, gw.data(), sizeof(float) * (pad + 1), hipMemcpyHostToDevice) != hipSuccess ||
+    {
+        // compile-time tap counts of the stencil (register arrays up to 26 entries
+        // stay in VGPRs with uniform indexing; wider stencils are rejected above)
+        static const int tpads[] = {4, 6, 9, 12, 16, 20, 25};
+        g->tpad = 0;
+        for (int t : tpads)
+            if (t >= pad) { g->tpad = t; break; }
+    }
+    std::vector<float> gw64(std::max(pad + 1, 64), 0.0f);
+    std::copy(gw.begin(), gw.end(), gw64.begin());
+    if (hipMemcpy(g->d_gw, gw64.data(), sizeof(float) * gw64.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(g->d_aof, aof.data(), sizeof(int) * (pad + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(g->d_push, push.data(), sizeof(int4) * push.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(g->d_push_off, push_off.data(), sizeof(int) * (s + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_tab, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(g->d_counters, 0, sizeof(unsigned) * (size_t)max_batch) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         free_grid(g);

@@ -70,7 +70,7 @@ CASES = {
     "realistic": (W.workload("realistic").spec, (38.0, 33.6), 3),
     "ragged_s3_2d_hq": (W.GridSpec(37, 23, 0.2, 3, 1.2, 1, 2, W.HALO_HERNQUIST), (15.0, 9.0), 6),
     "nobulge_1d": (W.GridSpec(29, 31, 0.15, 3, 0.9, 0, 1, W.HALO_NFW), None, 6),
-    "nobulge_2d_nohalo": (W.GridSpec(24, 18, 0.25, 1, 2.0, 0, 2, W.HALO_NONE), None, 6),
+    "nobulge_2d_nohalo": (W.GridSpec(24, 18, 0.25, 1, 1.6, 0, 2, W.HALO_NONE), None, 6),
     "bulge_only_s5": (W.GridSpec(17, 19, 0.3, 5, 0.7, 1, 0, W.HALO_NONE), (7.0, 8.0), 4),
     "no_psf": (W.GridSpec(21, 20, 0.2, 3, 0.0, 1, 1, W.HALO_NFW), None, 4),
 }
