@@ -122,6 +122,8 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+typedef const __attribute__((address_space(4))) int* const_int_ptr;
+
 // One pixel-row step of the separable stencil for one (map, pixel column).
 // The step's s lattice rows (phases) each give horizontal partial sums
 // H_0..H_PAD at the pixel centre from one batch of LDS loads; the pixel row
@@ -129,7 +131,7 @@ __device__ inline double wave_sum(double v) {
 // acc[d] holds the running PSF sum of the pixel row d steps back; it is
 // shifted by one each step, so acc[D] is complete after this call.
 template <int PAD>
-__device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rstride, int s, int D,
+__device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rstride, int s,
                                             const float* __restrict__ gw, const int2* __restrict__ tab,
                                             float (&acc)[DMAX + 1]) {
     float g[PAD + 1];
@@ -144,12 +146,14 @@ __device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rs
         H[0] = g[0] * L[0];
 #pragma unroll
         for (int k = 1; k <= PAD; ++k) H[k] = fmaf(g[k], L[-k] + L[k], H[k - 1]);
-        const int2* t = tab + ph * DSTRIDE;
+        // table entries through the constant address space: scalar loads; lags
+        // beyond D have weight 0, so the loop has a fixed trip count
+        const_int_ptr t = (const_int_ptr)tab + 2 * ph * DSTRIDE;
 #pragma unroll
         for (int d = 0; d <= DMAX; ++d) {
-            if (d > D) break;
-            const int2 e = t[d];
-            con[d] = fmaf(__int_as_float(e.y), H[e.x], con[d]);
+            const int A = t[2 * d];
+            const float w = __int_as_float(t[2 * d + 1]);
+            con[d] = fmaf(w, H[A], con[d]);
         }
     }
 #pragma unroll
@@ -237,9 +241,12 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
     const float invW = a.invW;
     double chi2 = 0.0;
     const size_t mapoff = (size_t)b * 4 * G.ny * G.nx;
-    // one (map, pixel column) pair per thread: blockDim >= 4 * band_w
-    const int pm = tid / NC, pc = tid - (tid / NC) * NC;
+    // one (map, pixel column) pair per thread: blockDim >= 4 * band_w; the
+    // threads beyond 4 NC run the same code on a clamped pair and store nothing,
+    // which keeps the stencil phase free of divergent control flow
     const bool pact = tid < 4 * NC;
+    const int tcl = pact ? tid : 4 * NC - 1;
+    const int pm = tcl / NC, pc = tcl - (tcl / NC) * NC;
     float acc[DMAX + 1];
 #pragma unroll
     for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0f;
@@ -260,26 +267,37 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
         for (int k = 1; k <= RS_CAP; ++k) npts = (k == nrow) ? st[k] : npts;
         // ---- data of the pixel rows completed in this phase (prefetched)
         float pv[GSUB_CAP], pi[GSUB_CAP];
-        if (MODE != MODE_MAPS && pact) {
+        if (MODE != MODE_MAPS) {
 #pragma unroll
             for (int k = 0; k < GSUB_CAP; ++k) {
                 if (k >= a.gsub) break;
                 const int jj = q0 + k - D;
                 const bool ok = jj >= 0 && jj < NR;
                 const size_t pix = ((size_t)pm * G.ny + j0 + (ok ? jj : 0)) * G.nx + c0 + pc;
-                pv[k] = ok ? a.val[pix] : 0.0f;
-                pi[k] = ok ? a.ivar[pix] : 0.0f;
+                const float vv = a.val[pix], ii = a.ivar[pix];
+                pv[k] = vv;
+                pi[k] = (ok && pact) ? ii : 0.0f;
             }
         }
         // ---- model phase: the phase's lattice points, flat over its rows
         for (int q = tid; q < npts; q += BS) {
+            // row of point q: compare with every row start (entries past the
+            // phase's rows are huge), no data-dependent indexing
             int lr = 0, rowq = 0;
+            if (nrow <= 8) {
 #pragma unroll
-            for (int k = 1; k < RS_CAP; ++k) {
-                if (k >= nrow) break;
-                const bool ge = q >= st[k];
-                lr += ge ? 1 : 0;
-                rowq = ge ? st[k] : rowq;
+                for (int k = 1; k < 8; ++k) {
+                    const bool ge = q >= st[k];
+                    lr += ge ? 1 : 0;
+                    rowq = ge ? st[k] : rowq;
+                }
+            } else {
+#pragma unroll
+                for (int k = 1; k < RS_CAP; ++k) {
+                    const bool ge = q >= st[k];
+                    lr += ge ? 1 : 0;
+                    rowq = ge ? st[k] : rowq;
+                }
             }
             const int r = rA + lr;
             const int x = s_lo[r] + (q - rowq);                 // local column
@@ -297,14 +315,14 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
         }
         __syncthreads();
         // ---- stencil phase: per (map, column) pair, in registers
-        if (pact) {
+        {
 #pragma unroll
             for (int k = 0; k < GSUB_CAP; ++k) {
                 if (k >= a.gsub) break;
                 const int q = q0 + k;
                 if (q >= Q) break;
                 const float* L0 = s_rows + (k * s) * 4 * XW + pm * XW + pc * s + pad;
-#define GK_SUB(PADV) stencil_sub<PADV>(L0, 4 * XW, s, D, a.gw, a.tab, acc)
+#define GK_SUB(PADV) stencil_sub<PADV>(L0, 4 * XW, s, a.gw, a.tab, acc)
                 switch (a.tpad) {
                     case 4: GK_SUB(4); break;
                     case 6: GK_SUB(6); break;
@@ -320,7 +338,7 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
                     const float F = acc[D] * invW;
                     const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
                     if (MODE == MODE_MAPS) {
-                        a.maps[mapoff + pix] = (pm == 3) ? 1.0f / F : F;
+                        if (pact) a.maps[mapoff + pix] = (pm == 3) ? 1.0f / F : F;
                     } else {
                         const float iv = pi[k];
                         float gbar = 0.0f;
@@ -331,7 +349,7 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
                             // d logL / dF: -iv res, and for M/L = 1/F: +iv res / F^2
                             gbar = (pm == 3) ? iv * res * Fm * Fm : -iv * res;
                         }
-                        if (MODE == MODE_FBAR) a.fbar[mapoff + pix] = gbar;
+                        if (MODE == MODE_FBAR && pact) a.fbar[mapoff + pix] = gbar;
                     }
                 }
             }
