@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one 512 MiB device copy (traffic-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -286,6 +288,14 @@ def main():
             "flop_per_vector": flop_theta,
             "per_unit": {"lattice_points": n_need, "flop_per_point": flops_per_point(spec),
                          "valid_spaxels": n_valid, "flop_per_spaxel": flops_per_pixel(spec)}}
+
+    if args.copy_calib:
+        src_buf = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst_buf = torch.empty_like(src_buf)
+        torch.cuda.synchronize()
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
 
     # ---- CPU baseline (oracle, unchanged)
     cpu = None
