@@ -113,6 +113,39 @@ int loglike_grad_batch(gk_grid_t grid, const double* theta, int B, int stride, d
 int eval_maps(gk_grid_t grid, const double* theta, int B, int stride, float* maps,
               void* hip_stream);
 
+/* Hamiltonian Monte Carlo trajectory of n_steps leapfrog steps for every
+ * row (the gradient-driven sampler pattern the adjoint enables; not a method
+ * of the paper, which uses nested sampling, Sec. 2.5).  With H = -logL(theta)
+ * + p^T M^-1 p / 2: half kick p += (eps/2) grad, then n_steps times a drift
+ * theta += eps M^-1 p followed by a full kick (half kick after the last
+ * drift).  theta, momentum: device float64 [B][stride], updated in place;
+ * inv_mass: device float64 [P] (diagonal M^-1); logL, grad: device outputs
+ * (log-likelihood and gradient at the final position).  Rows with a
+ * non-finite log-likelihood are frozen.  Enqueues n_steps + 1 gradient
+ * evaluations and updates on the stream; allocates nothing, so a call can be
+ * captured once in a HIP graph and replayed. */
+int hmc_leapfrog(gk_grid_t grid, double* theta, double* momentum, const double* inv_mass, double eps,
+                 int n_steps, int B, int stride, double* logL, double* grad, void* hip_stream);
+
+/* Log-likelihoods of many galaxies in ONE persistent launch (the batched
+ * form of the paper's per-galaxy likelihood, Sec. 2.5.1, over a catalogue).
+ * grids: host array of n_gal distinct handles (all with data, all on the
+ * current device).  theta_offset: host int array [n_gal + 1], theta_offset[0]
+ * = 0, non-decreasing; rows theta_offset[g] .. theta_offset[g+1]-1 of theta
+ * (device float64 [rows][stride], stride >= every grid's P) belong to galaxy g
+ * and number at most that grid's max_batch; logL: device float64 [rows].
+ * Workgroups take (galaxy, row, pixel band) items from a device queue in
+ * decreasing cost order.  The first call with a given (grids, theta_offset,
+ * launch shapes) builds and uploads that work plan (allocating and
+ * synchronising); repeated calls with the same arguments only enqueue the
+ * launch and may then be captured in a HIP graph.  A destroyed grid's plans
+ * are dropped.  grad (device float64 [rows][stride]) may be NULL; if given, the
+ * gradient is computed as well, by one forward + adjoint launch pair per
+ * galaxy.  The grids' workspaces are used: no other call on these grids may
+ * run concurrently. */
+int loglike_multi(const gk_grid_t* grids, int n_gal, const double* theta, const int* theta_offset,
+                  int stride, double* logL, double* grad, void* hip_stream);
+
 /* Launch shape used for batches of size >= batch_min (band of band_h x band_w
  * pixels per workgroup; the autotuner sets these).  band_h, band_w >= 1. */
 int set_launch_shape(gk_grid_t grid, int batch_min, int band_h, int band_w);

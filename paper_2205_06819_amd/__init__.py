@@ -6,7 +6,7 @@ Thin Python binding of the C-ABI library ``libgalkin.so`` (declared in
 entry points and only marshal arguments: every step of the likelihood runs
 in the HIP kernels.  PyTorch supplies device memory and streams.
 
-If the library has not been built (``python -m paper_2205_06819_amd.build``),
+If the library has not been built (``python paper_2205_06819_amd/build.py``),
 importing this package raises an error: there is no CPU fallback.
 """
 from __future__ import annotations
@@ -27,7 +27,7 @@ GK_BULGE_NONE, GK_BULGE_HERNQUIST = 0, 1
 GK_HALO_NONE, GK_HALO_HERNQUIST, GK_HALO_NFW = 0, 1, 2
 
 EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",
-           "loglike_grad_batch", "eval_maps", "set_launch_shape", "last_error")
+           "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "last_error")
 
 
 class GalkinError(RuntimeError):
@@ -45,8 +45,11 @@ class GridDesc(ctypes.Structure):
 
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2205_06819_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2205_06819_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
+    missing = [n for n in EXPORTS if not hasattr(lib, n)]
+    if missing:
+        raise ImportError(f"{LIB_PATH} lacks {missing}: rebuild it with `python paper_2205_06819_amd/build.py`")
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lib.create_grid.argtypes = [ctypes.POINTER(GridDesc), i, ctypes.POINTER(vp)]
     lib.destroy_grid.argtypes = [vp]
@@ -56,6 +59,8 @@ def _load() -> ctypes.CDLL:
     lib.loglike_grad_batch.argtypes = [vp, vp, i, i, vp, vp, vp]
     lib.eval_maps.argtypes = [vp, vp, i, i, vp, vp]
     lib.set_launch_shape.argtypes = [vp, i, i, i]
+    lib.hmc_leapfrog.argtypes = [vp, vp, vp, vp, d, i, i, i, vp, vp, vp]
+    lib.loglike_multi.argtypes = [vp, i, vp, vp, i, vp, vp, vp]
     lib.last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "last_error":
@@ -162,6 +167,46 @@ def eval_maps(handle: int, theta: torch.Tensor, ny: int, nx: int,
         out = torch.empty(B, 4, ny, nx, dtype=torch.float32, device=theta.device)
     _check(_lib.eval_maps(handle, theta.data_ptr(), B, theta.stride(0), out.data_ptr(),
                           _stream(stream)))
+    return out
+
+
+def hmc_leapfrog(handle: int, theta: torch.Tensor, momentum: torch.Tensor, inv_mass: torch.Tensor,
+                 eps: float, n_steps: int, logL: torch.Tensor, grad: torch.Tensor, stream=None) -> None:
+    """In-place leapfrog trajectory (see include/galkin.h); all tensors on the device."""
+    P = n_params(handle)
+    for t, nm in ((theta, "theta"), (momentum, "momentum"), (grad, "grad")):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1):
+            raise ValueError(f"{nm} must be a contiguous-row float64 CUDA tensor [B, stride]")
+    if momentum.stride(0) != theta.stride(0) or grad.stride(0) != theta.stride(0):
+        raise ValueError("theta, momentum and grad must share the row stride")
+    if inv_mass.numel() < P or inv_mass.dtype != torch.float64 or not inv_mass.is_cuda:
+        raise ValueError("inv_mass must be a float64 CUDA tensor with P entries")
+    _check(_lib.hmc_leapfrog(handle, theta.data_ptr(), momentum.data_ptr(), inv_mass.data_ptr(),
+                             float(eps), int(n_steps), theta.shape[0], theta.stride(0),
+                             logL.data_ptr(), grad.data_ptr(), _stream(stream)))
+
+
+def loglike_multi(handles, theta: torch.Tensor, theta_offset, out: Optional[torch.Tensor] = None,
+                  grad: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Log-likelihoods of many grids in one launch.  Rows theta_offset[g] ..
+    theta_offset[g+1]-1 of theta belong to grid handles[g]; theta has as many
+    columns as the largest parameter count.  With grad given (float64
+    [rows, stride]) the gradient is written too."""
+    n = len(handles)
+    offs = np.ascontiguousarray(np.asarray(theta_offset, dtype=np.int32))
+    if offs.shape != (n + 1,):
+        raise ValueError("theta_offset needs len(handles) + 1 entries")
+    if not (theta.is_cuda and theta.dtype == torch.float64 and theta.dim() == 2 and theta.stride(1) == 1):
+        raise ValueError("theta must be a contiguous-row float64 CUDA tensor [rows, stride]")
+    if theta.shape[0] < int(offs[-1]):
+        raise ValueError("theta has fewer rows than theta_offset[-1]")
+    hs = (ctypes.c_void_p * max(1, n))(*[ctypes.c_void_p(h) for h in handles])
+    if out is None:
+        out = torch.empty(int(offs[-1]), dtype=torch.float64, device=theta.device)
+    if grad is not None and (grad.stride(0) != theta.stride(0) or grad.stride(1) != 1 or grad.dtype != torch.float64):
+        raise ValueError("grad must be float64 with theta's row stride")
+    _check(_lib.loglike_multi(hs, n, theta.data_ptr(), offs.ctypes.data, theta.stride(0), out.data_ptr(),
+                              _ptr(grad), _stream(stream)))
     return out
 
 

@@ -1,6 +1,8 @@
 """Build the HIP shared library libgalkin.so for gfx950, in-tree.
 
-    python -m paper_2205_06819_amd.build
+    python paper_2205_06819_amd/build.py
+
+(run by path: importing the package would load the library being rebuilt).
 
 Compiles paper_2205_06819_amd/csrc/galkin.hip with hipcc into
 paper_2205_06819_amd/libgalkin.so.  Packed FP32 instructions are disabled

@@ -24,6 +24,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,8 +48,9 @@ struct FwdArgs {
     const float* val;       // data [4][ny][nx]
     const float* ivar;      // inverse variances [4][ny][nx], 0 = masked
     const int2* span;       // [ny] first / last column valid in any map
-    double logdet;          // sum of ln(2 pi e^2) over valid pixels
+    const double* logdet;   // sum of ln(2 pi e^2) over valid pixels (device scalar)
     int band_h, band_w, nbx, nbands;
+    int pstride;            // row stride of partials (>= nbands)
     int gsub;               // pixel-row steps per model phase (gsub * s <= RS_CAP lattice rows)
     int xw;                 // row stride of the row buffer (floats)
     int tpad;               // compile-time tap count used by the stencil (>= pad)
@@ -57,7 +59,7 @@ struct FwdArgs {
     double* logL;
     float* maps;            // MODE_MAPS output [B][4][ny][nx]
     float* fbar;            // MODE_FBAR output [B][4][ny][nx]: d logL / d F
-    double* partials;       // [B][nbands]
+    double* partials;       // [B][pstride]
     unsigned* counters;     // [B]
 };
 
@@ -161,12 +163,12 @@ __device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rs
     acc[0] = con[0];
 }
 
+// One parameter vector (row b) on one band of one grid.  load_tables = false
+// when the caller already staged the special-function tables in LDS.
 template <int BULGE, int NDISC, int HALO, int MODE>
-__global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
-    extern __shared__ __align__(16) float smem[];
+__device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const int band, float* smem,
+                                         const bool load_tables) {
     const int tid = threadIdx.x, BS = blockDim.x;
-    const int band = blockIdx.x % a.nbands;
-    const int b = blockIdx.x / a.nbands;
     const GridGeom& G = a.geo;
     const int s = G.s, pad = G.pad, hs = G.hs;
     const int by = band / a.nbx, bx = band - by * a.nbx;
@@ -203,9 +205,11 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
     }
 
     // --- prologue: tables, zeroed row buffer, row spans
-    for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = gk_tab_gh[i];
-    for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
-    for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
+    if (load_tables) {
+        for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = gk_tab_gh[i];
+        for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
+        for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
+    }
     for (int i = tid; i < RS * 4 * XW; i += BS) s_rows[i] = 0.0f;
     for (int r = tid; r < NFR; r += BS) {
         const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;   // ceil((r - 2 pad) / s)
@@ -367,21 +371,341 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
         double t = 0.0;
         for (int w = 0; w < (BS + 63) / 64; ++w) t += s_red[w];
         if (a.nbands == 1) {
-            a.logL[b] = -0.5 * (t + a.logdet);
+            a.logL[b] = -0.5 * (t + *a.logdet);
         } else {
-            a.partials[(size_t)b * a.nbands + band] = t;
+            a.partials[(size_t)b * a.pstride + band] = t;
             const unsigned ticket = __hip_atomic_fetch_add(a.counters + b, 1u, __ATOMIC_ACQ_REL,
                                                            __HIP_MEMORY_SCOPE_AGENT);
             if (ticket == (unsigned)a.nbands - 1) {
                 double sum = 0.0;
                 for (int k = 0; k < a.nbands; ++k)
-                    sum += __hip_atomic_load(a.partials + (size_t)b * a.nbands + k, __ATOMIC_RELAXED,
+                    sum += __hip_atomic_load(a.partials + (size_t)b * a.pstride + k, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
-                a.logL[b] = -0.5 * (sum + a.logdet);
+                a.logL[b] = -0.5 * (sum + *a.logdet);
                 __hip_atomic_store(a.counters + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
+}
+
+template <int BULGE, int NDISC, int HALO, int MODE>
+__global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
+    extern __shared__ __align__(16) float smem[];
+    fwd_band<BULGE, NDISC, HALO, MODE>(a, blockIdx.x / a.nbands, blockIdx.x % a.nbands, smem, true);
+}
+
+// ============================================================================
+// many grids in one persistent launch: workgroups take work items (grid,
+// parameter row within the grid, band, first row of the grid in the batch)
+// from an atomic queue; the host orders the items by decreasing cost
+// ============================================================================
+typedef const __attribute__((address_space(4))) int* const_word_ptr;
+
+constexpr int MULTI_BS = 256;   // threads per workgroup of the many-grid launch
+
+__global__ void __launch_bounds__(MULTI_BS) __attribute__((amdgpu_waves_per_eu(2)))
+multi_kernel(const FwdArgs* __restrict__ grids,
+                                                    const int4* __restrict__ items, int n_items,
+                                                    const double* theta, int stride, double* logL,
+                                                    unsigned* work) {
+    extern __shared__ __align__(16) float smem[];
+    __shared__ int s_item;
+    const int tid = threadIdx.x, BS = blockDim.x;
+    for (int i = tid; i < TAB_GH; i += BS) smem[i] = gk_tab_gh[i];
+    for (int i = tid; i < TAB_PHI; i += BS) smem[TAB_GH + i] = gk_tab_phi[i];
+    for (int i = tid; i < TAB_M; i += BS) smem[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (int)__hip_atomic_fetch_add(work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int it = uni(s_item);
+        if (it >= n_items) break;
+        const_word_ptr iw = (const_word_ptr)(items) + 4 * it;
+        const int g = iw[0], row = iw[1], band = iw[2], off = iw[3];
+        // this grid's parameters, word by word through scalar loads
+        union {
+            FwdArgs a;
+            int w[sizeof(FwdArgs) / 4];
+        } u;
+        {
+            constexpr int NW = (int)(sizeof(FwdArgs) / 4);
+            const_word_ptr src = (const_word_ptr)(grids) + (size_t)g * NW;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) u.w[k] = src[k];
+        }
+        FwdArgs& a = u.a;
+        a.theta = theta + (size_t)off * stride;   // this grid's rows start at row off
+        a.stride = stride;
+        a.logL = logL + off;
+        const int comp = a.geo.bulge * 100 + a.geo.ndisc * 10 + a.geo.halo;
+        switch (comp) {
+#define GK_MCASE(BU, ND, HA)                                                                   \
+    case BU * 100 + ND * 10 + HA:                                                              \
+        fwd_band<BU, ND, HA, MODE_LOGL>(a, row, band, smem, false);                             \
+        break;
+            GK_MCASE(1, 0, 0) GK_MCASE(1, 0, 1) GK_MCASE(1, 0, 2)
+            GK_MCASE(1, 1, 0) GK_MCASE(1, 1, 1) GK_MCASE(1, 1, 2)
+            GK_MCASE(1, 2, 0) GK_MCASE(1, 2, 1) GK_MCASE(1, 2, 2)
+            GK_MCASE(0, 1, 0) GK_MCASE(0, 1, 1) GK_MCASE(0, 1, 2)
+            GK_MCASE(0, 2, 0) GK_MCASE(0, 2, 1) GK_MCASE(0, 2, 2)
+#undef GK_MCASE
+            default: break;
+        }
+    }
+    // the last workgroup out re-arms the queue for the next launch
+    if (tid == 0) {
+        const unsigned out = __hip_atomic_fetch_add(work + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (out == gridDim.x - 1) {
+            __hip_atomic_store(work, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(work + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ============================================================================
+// adjoint: d logL / d theta
+// ============================================================================
+constexpr int MAX_BANDS_ADJ = 64;
+
+struct AdjArgs {
+    GridGeom geo;
+    const float* gw;        // [64] 1-D Gaussian factors
+    const int* aof;         // [pad + 1] stencil half-widths
+    float invW;
+    const int2* span;       // [ny] valid column spans
+    int band_h, band_w, nbx, nbands;
+    const double* theta;
+    int stride;
+    const float* fbar;      // [B][4][ny][nx] d logL / d F from the forward pass
+    double* gpart;          // [B][nbands][NCONST] per-band constant adjoints
+    unsigned* counters;     // [B], zero on entry, reset by the last band
+    double* grad;           // [B][stride]
+};
+
+__host__ __device__ inline int adj_lds_bytes(int band_h, int band_w, int s, int pad) {
+    const int nfrm = nfr_max(band_h, s, pad);
+    return 4 * (TAB_ALL + 4 * band_h * band_w + 64 + 2 * nfrm + 1 + RED_SLOTS * 2 * NCONST + 64);
+}
+
+__device__ inline int floor_div(int n, int d) { return n >= 0 ? n / d : -((-n + d - 1) / d); }
+
+// Chain rule from the adjoints of the FP32 constants of make_tc to the
+// parameters (FP64), then writes the gradient row (zeros past P).
+__device__ inline void chain_rule(const double* th, const GridGeom& g, const double* cb, double* out,
+                                  int stride) {
+    const double d2r = PI / 180.0, LN10 = 2.302585092994046;
+    double gr[32];
+    for (int k = 0; k < 32; ++k) gr[k] = 0.0;
+    const double pa = th[2] * d2r, inc = th[3] * d2r;
+    double spa, cpa, si, ci;
+    sincos(pa, &spa, &cpa);
+    sincos(inc, &si, &ci);
+    const double pks = g.pk / g.s;
+    gr[0] = cb[C_UF] * g.s;
+    gr[1] = cb[C_VF] * g.s;
+    gr[2] = (cb[C_CA] * (-pks * spa) + cb[C_SA] * (pks * cpa)) * d2r;
+    gr[3] = cb[C_SEC2I] * 2.0 * si / (ci * ci * ci) * d2r;
+    int k = 4;
+    if (g.bulge) {
+        const double Mb = exp10(th[k]), Rb = th[k + 1], ML = th[k + 2];
+        const double Ab = 1.0e-6 * Mb / (2.0 * PI * Rb * Rb * ML);
+        const double Cb = 1.0e-6 * G_KPC * Mb * Mb / (12.0 * PI * Rb * Rb * Rb * ML);
+        const double GMb = G_KPC * Mb;
+        gr[k] = (cb[C_AB] * Ab + 2.0 * cb[C_CB] * Cb + cb[C_GMB] * GMb) * LN10;
+        gr[k + 1] = -cb[C_INVRB] / (Rb * Rb) - 2.0 * cb[C_AB] * Ab / Rb - 3.0 * cb[C_CB] * Cb / Rb + cb[C_RB];
+        gr[k + 2] = -cb[C_AB] * Ab / ML - cb[C_CB] * Cb / ML + cb[C_MLB];
+        k += 3;
+    }
+    for (int j = 0; j < g.ndisc; ++j) {
+        const int o = C_D0 + 7 * j;
+        const double Md = exp10(th[k]), Rd = th[k + 1], ML = th[k + 2], kk = th[k + 3];
+        const double nl2Rd = -1.4426950408889634 / Rd;
+        const double Ad = 1.0e-6 * Md / (2.0 * PI * Rd * Rd * ci * ML);
+        const double inv2Rd = 0.5 / Rd;
+        const double Kd = 2.0 * G_KPC * Md / Rd;
+        gr[k] = (cb[o + 1] * Ad + cb[o + 3] * Kd) * LN10;
+        gr[k + 1] = -(cb[o + 0] * nl2Rd + 2.0 * cb[o + 1] * Ad + cb[o + 2] * inv2Rd + cb[o + 3] * Kd) / Rd;
+        gr[k + 2] = -cb[o + 1] * Ad / ML + cb[o + 6];
+        gr[k + 3] = -cb[o + 4] * si - cb[o + 5] * 2.0 * kk / 3.0;
+        gr[3] += (cb[o + 1] * Ad * si / ci - cb[o + 4] * kk * ci) * d2r;
+        k += 4;
+    }
+    if (g.halo == 2) {
+        const double M200 = exp10(th[k]), conc = th[k + 1];
+        const double r200 = cbrt(3.0 * M200 / (4.0 * PI * 200.0 * g.rho_crit));
+        const double rs = r200 / conc;
+        const double muc = log1p(conc) - conc / (1.0 + conc);
+        const double H0 = 1.0 / rs, H1 = G_KPC * M200 / (rs * muc);
+        const double dmu = conc / ((1.0 + conc) * (1.0 + conc));
+        gr[k] = (-cb[C_H0] * H0 / 3.0 + cb[C_H1] * H1 * 2.0 / 3.0) * LN10;
+        gr[k + 1] = cb[C_H0] / r200 + cb[C_H1] * H1 * (1.0 / conc - dmu / muc);
+        k += 2;
+    } else if (g.halo == 1) {
+        const double H1 = G_KPC * exp10(th[k]);
+        gr[k] = cb[C_H1] * H1 * LN10;
+        gr[k + 1] = cb[C_H0];
+        k += 2;
+    }
+    for (int q = 0; q < stride; ++q) out[q] = q < k ? gr[q] : 0.0;
+}
+
+template <int BULGE, int NDISC, int HALO>
+__global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
+    extern __shared__ __align__(16) float smem[];
+    const int tid = threadIdx.x, BS = blockDim.x;
+    const int band = blockIdx.x % a.nbands;
+    const int b = blockIdx.x / a.nbands;
+    const GridGeom& G = a.geo;
+    const int s = G.s, pad = G.pad, hs = G.hs;
+    const int by = band / a.nbx, bx = band - by * a.nbx;
+    const int j0 = by * a.band_h, j1 = min(G.ny, j0 + a.band_h);
+    const int c0 = bx * a.band_w, c1 = min(G.nx, c0 + a.band_w);
+    const int NR = j1 - j0, NC = c1 - c0;
+    const int NFR = (NR - 1) * s + 2 * pad + 1;
+    const int vlo = j0 * s + hs, ubase = c0 * s + hs;
+    const int nfrm = nfr_max(a.band_h, s, pad);
+    float* s_tab = smem;
+    float4* s_fb = (float4*)(smem + TAB_ALL);                    // [NR][NC]
+    float* s_gw = smem + TAB_ALL + 4 * a.band_h * a.band_w;       // [64]
+    int* s_lo = (int*)(s_gw + 64);
+    int* s_start = s_lo + nfrm;                                    // [nfrm + 1]
+    double* s_red = (double*)(((uintptr_t)(s_start + nfrm + 1) + 15) & ~(uintptr_t)15);
+
+    const double* th = a.theta + (size_t)b * a.stride;
+    const TC tc = uniform_tc(make_tc(th, G));
+    if (!tc.valid) {
+        if (band == 0)
+            for (int q = tid; q < a.stride; q += BS) a.grad[(size_t)b * a.stride + q] = 0.0;
+        return;
+    }
+    for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = gk_tab_gh[i];
+    for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
+    for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
+    for (int i = tid; i < 64; i += BS) s_gw[i] = a.gw[i];
+    const size_t boff = (size_t)b * 4 * G.ny * G.nx, mstr = (size_t)G.ny * G.nx;
+    for (int p = tid; p < NR * NC; p += BS) {
+        const int jj = p / NC, cc = p - jj * NC;
+        const size_t pix = boff + (size_t)(j0 + jj) * G.nx + c0 + cc;
+        s_fb[p] = make_float4(a.fbar[pix], a.fbar[pix + mstr], a.fbar[pix + 2 * mstr], a.fbar[pix + 3 * mstr]);
+    }
+    for (int r = tid; r < NFR; r += BS) {
+        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
+        const int jhi = min(NR - 1, r / s);
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int jj = jlo; jj <= jhi; ++jj) {
+            int bb = r - jj * s - pad;
+            bb = bb < 0 ? -bb : bb;
+            const int2 sp = a.span[j0 + jj];
+            const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
+            if (cl <= ch) {
+                const int A = a.aof[bb];
+                lo = min(lo, cl * s + hs + pad - A);
+                hi = max(hi, ch * s + hs + pad + A);
+            }
+        }
+        const int w = hi >= lo ? hi - lo + 1 : 0;
+        s_lo[r] = w ? lo - ubase : 0;
+        s_start[r] = w;
+    }
+    __syncthreads();
+    const int total = block_exclusive_scan(s_start, NFR, (int*)s_red);
+    if (tid == 0) s_start[NFR] = total;
+    __syncthreads();
+
+    const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
+                 (const float4*)(s_tab + TAB_GH + TAB_PHI)};
+    float ad[NCONST];
+#pragma unroll
+    for (int k = 0; k < NCONST; ++k) ad[k] = 0.0f;
+    const float invW = a.invW;
+    int rcur = 0;
+    for (int q = tid; q < total; q += BS) {
+        while (s_start[rcur + 1] <= q) ++rcur;
+        const int r = rcur;
+        const int x = s_lo[r] + (q - s_start[r]);
+        // transposed stencil: this lattice point's share of every band pixel
+        // whose 3 sigma disc contains it, weighted by that pixel's adjoint
+        float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
+        const int jhi = min(NR - 1, r / s);
+        for (int jj = jlo; jj <= jhi; ++jj) {
+            int bb = r - jj * s - pad;
+            bb = bb < 0 ? -bb : bb;
+            const int A = a.aof[bb];
+            const float gb = s_gw[bb];
+            const int ccl = max(0, -floor_div(-(x - pad - A), s));
+            const int cch = min(NC - 1, floor_div(x - pad + A, s));
+            for (int cc = ccl; cc <= cch; ++cc) {
+                int aa = x - cc * s - pad;
+                aa = aa < 0 ? -aa : aa;
+                const float w = gb * s_gw[aa];
+                const float4 fb = s_fb[jj * NC + cc];
+                f.x = fmaf(w, fb.x, f.x);
+                f.y = fmaf(w, fb.y, f.y);
+                f.z = fmaf(w, fb.z, f.z);
+                f.w = fmaf(w, fb.w, f.w);
+            }
+        }
+        const float du = (float)(ubase + x - tc.Ui) - tc.Uf;
+        const float dv = (float)(vlo + r - tc.Vi) - tc.Vf;
+        point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, f.x * invW, f.y * invW, f.z * invW, f.w * invW, ad);
+    }
+
+    // ---- FP64 reduction of the constant adjoints: waves, then bands in order
+    const int lane = tid & 63, wave = tid >> 6, nw = (BS + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < NCONST; ++k) {
+        const double v = wave_sum((double)ad[k]);
+        if (lane == 0) s_red[wave * NCONST + k] = v;
+    }
+    __syncthreads();
+    double* gp = a.gpart + ((size_t)b * a.nbands + band) * NCONST;
+    if (tid < NCONST) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += s_red[w * NCONST + tid];
+        gp[tid] = t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        bool last = true;
+        if (a.nbands > 1) {
+            const unsigned ticket = __hip_atomic_fetch_add(a.counters + b, 1u, __ATOMIC_ACQ_REL,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            last = ticket == (unsigned)a.nbands - 1;
+        }
+        if (last) {
+            double cb[NCONST];
+            for (int k = 0; k < NCONST; ++k) cb[k] = 0.0;
+            for (int bnd = 0; bnd < a.nbands; ++bnd)
+                for (int k = 0; k < NCONST; ++k)
+                    cb[k] += __hip_atomic_load(a.gpart + ((size_t)b * a.nbands + bnd) * NCONST + k,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            chain_rule(th, G, cb, a.grad + (size_t)b * a.stride, a.stride);
+            if (a.nbands > 1) __hip_atomic_store(a.counters + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ============================================================================
+// HMC leapfrog update (elementwise over the batch)
+// ============================================================================
+// stage 0: p += h g (half kick), then theta += eps M^-1 p (drift)
+// stage 1: p += eps g, then drift
+// stage 2: p += h g (closing half kick), no drift
+// Rows whose log-likelihood is not finite are frozen (no update).
+__global__ void __launch_bounds__(256) leapfrog_kernel(double* theta, double* mom, const double* grad,
+                                                       const double* logL, const double* inv_mass,
+                                                       double eps, int stage, int B, int P, int stride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * P) return;
+    const int b = i / P, k = i - b * P;
+    const double L = logL[b];
+    if (!(L > -INFINITY && L < INFINITY)) return;
+    const size_t o = (size_t)b * stride + k;
+    const double kick = (stage == 1) ? eps : 0.5 * eps;
+    double p = mom[o] + kick * grad[o];
+    mom[o] = p;
+    if (stage != 2) theta[o] += eps * inv_mass[k] * p;
 }
 
 }  // namespace gk
@@ -430,7 +754,10 @@ struct gk_grid {
     double* d_partials = nullptr;
     unsigned* d_counters = nullptr;
     float* d_fbar = nullptr;
+    double* d_gpart = nullptr;
+    double* d_logdet = nullptr;
     std::vector<LaunchRule> rules;
+    int adj_band_h = 0, adj_band_w = 0;
 };
 
 static int valid_desc(const gk_grid_desc* d) {
@@ -455,7 +782,7 @@ static int valid_desc(const gk_grid_desc* d) {
 
 static void free_grid(gk_grid* g) {
     void* bufs[] = {g->d_gw, g->d_aof, g->d_tab, g->d_val, g->d_ivar,
-                    g->d_span, g->d_partials, g->d_counters, g->d_fbar};
+                    g->d_span, g->d_partials, g->d_counters, g->d_fbar, g->d_gpart, g->d_logdet};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete g;
@@ -490,7 +817,7 @@ struct LaunchCfg {
     int band_h, band_w, nbx, nbands, BS, gsub, xw, lds;
 };
 
-static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c) {
+static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int bs_fixed = 0) {
     const int s = g->geo.s, pad = g->geo.pad;
     c.band_h = band_h;
     c.band_w = band_w;
@@ -500,6 +827,10 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c) {
     if (c.nbands > MAX_BANDS) return fail(GK_EINVAL, "launch shape gives %d bands (> %d)", c.nbands, MAX_BANDS);
     if (band_w > 128) return fail(GK_EINVAL, "band_w %d > 128", band_w);
     c.BS = std::min(512, std::max(64, (4 * band_w + 63) / 64 * 64));
+    if (bs_fixed) {
+        if (4 * band_w > bs_fixed) return fail(GK_EINVAL, "band_w %d > %d", band_w, bs_fixed / 4);
+        c.BS = bs_fixed;
+    }
     c.xw = band_w * s + 2 * pad + 1;
     // pixel-row steps per model phase: about four lattice points per thread,
     // at most RS_CAP lattice rows, and the row buffer within ~40 KiB of LDS
@@ -550,7 +881,8 @@ static void fill_args(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, const do
     a.val = g->d_val;
     a.ivar = g->d_ivar;
     a.span = g->d_span;
-    a.logdet = g->logdet;
+    a.logdet = g->d_logdet;
+    a.pstride = MAX_BANDS;
     a.band_h = c.band_h;
     a.band_w = c.band_w;
     a.nbx = c.nbx;
@@ -565,6 +897,128 @@ static void fill_args(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, const do
     a.fbar = nullptr;
     a.partials = g->d_partials;
     a.counters = g->d_counters;
+}
+
+// ---------------------------------------------------------------------------
+// many-grid plans: the per-grid argument blocks and the cost-ordered work
+// items of one (grids, row offsets) combination, kept on the device so that a
+// repeated call only enqueues the launch
+// ---------------------------------------------------------------------------
+struct MultiPlan {
+    int device = 0;
+    std::vector<const gk_grid*> grids;
+    std::vector<int> offs;
+    std::vector<int> shapes;        // band_h, band_w per grid at build time
+    FwdArgs* d_args = nullptr;
+    int4* d_items = nullptr;
+    unsigned* d_work = nullptr;     // [0] next item, [1] workgroups done
+    int n_items = 0, n_wg = 0, lds = 0;
+};
+
+static std::mutex g_plan_mu;
+static std::vector<MultiPlan*> g_plans;   // most recently used last
+constexpr size_t MAX_PLANS = 8;
+
+static void free_plan(MultiPlan* p) {
+    if (p->d_args) (void)hipFree(p->d_args);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_work) (void)hipFree(p->d_work);
+    delete p;
+}
+
+// Drop every cached plan that uses grid g (called when g is destroyed).
+static void evict_plans(const gk_grid* g) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (size_t i = 0; i < g_plans.size();) {
+        MultiPlan* p = g_plans[i];
+        if (std::find(p->grids.begin(), p->grids.end(), g) != p->grids.end()) {
+            free_plan(p);
+            g_plans.erase(g_plans.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+static void multi_band_shape(const gk_grid* g, int rows, int& bh, int& bw) {
+    choose_rule(g, rows, bh, bw);
+    bw = std::min(bw, MULTI_BS / 4);
+}
+
+static bool plan_matches(const MultiPlan* p, int device, const gk_grid* const* grids, int n, const int* offs) {
+    if (p->device != device || (int)p->grids.size() != n) return false;
+    for (int i = 0; i < n; ++i) {
+        if (p->grids[i] != grids[i] || p->offs[i] != offs[i]) return false;
+        int bh, bw;
+        multi_band_shape(grids[i], offs[i + 1] - offs[i], bh, bw);
+        if (p->shapes[2 * i] != bh || p->shapes[2 * i + 1] != bw) return false;
+    }
+    return p->offs[n] == offs[n];
+}
+
+// Relative cost of one band of one row: model points plus stencil taps.
+static double band_cost(const gk_grid* g, const LaunchCfg& c, int band) {
+    const int s = g->geo.s, pad = g->geo.pad;
+    const int by = band / c.nbx, bx = band % c.nbx;
+    const int nr = std::min(g->d.ny, (by + 1) * c.band_h) - by * c.band_h;
+    const int nc = std::min(g->d.nx, (bx + 1) * c.band_w) - bx * c.band_w;
+    const double pts = (double)((nr - 1) * s + 2 * pad + 1) * ((nc - 1) * s + 2 * pad + 1);
+    const double ncomp = g->d.bulge + g->d.n_discs + (g->d.halo ? 1 : 0);
+    return pts * (60.0 + 35.0 * ncomp) + 4.0 * nr * nc * (4.0 * (s * (1 + 3 * pad) + 2 * (2 * pad + 1)));
+}
+
+static int build_plan(int device, const gk_grid* const* grids, int n, const int* offs, MultiPlan*& out) {
+    MultiPlan* p = new MultiPlan;
+    p->device = device;
+    p->grids.assign(grids, grids + n);
+    p->offs.assign(offs, offs + n + 1);
+    std::vector<FwdArgs> args(n);
+    struct Item { double cost; int4 it; };
+    std::vector<Item> items;
+    int lds = 0;
+    for (int i = 0; i < n; ++i) {
+        const gk_grid* g = grids[i];
+        const int rows = offs[i + 1] - offs[i];
+        int bh, bw;
+        multi_band_shape(g, rows, bh, bw);
+        p->shapes.push_back(bh);
+        p->shapes.push_back(bw);
+        LaunchCfg c;
+        int rc = make_cfg(g, bh, bw, c, MULTI_BS);
+        if (rc) { free_plan(p); return rc; }
+        lds = std::max(lds, c.lds);
+        fill_args(g, c, args[i], nullptr, 0);
+        for (int band = 0; band < c.nbands; ++band) {
+            const double cost = band_cost(g, c, band);
+            for (int r = 0; r < rows; ++r) items.push_back({cost, make_int4(i, r, band, offs[i])});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    std::vector<int4> it(items.size());
+    for (size_t k = 0; k < items.size(); ++k) it[k] = items[k].it;
+    p->n_items = (int)it.size();
+    p->lds = lds;
+    int per_cu = 0, n_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel, MULTI_BS, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        free_plan(p);
+        return fail(GK_EHIP, "occupancy query for the many-grid kernel failed");
+    }
+    p->n_wg = std::max(1, std::min(p->n_items, std::max(1, per_cu) * n_cu));
+    if (hipMalloc((void**)&p->d_args, sizeof(FwdArgs) * n) != hipSuccess ||
+        hipMalloc((void**)&p->d_items, sizeof(int4) * std::max<size_t>(1, it.size())) != hipSuccess ||
+        hipMalloc((void**)&p->d_work, 2 * sizeof(unsigned)) != hipSuccess) {
+        free_plan(p);
+        return fail(GK_ENOMEM, "allocation of a many-grid plan failed");
+    }
+    if (hipMemcpy(p->d_args, args.data(), sizeof(FwdArgs) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        (!it.empty() && hipMemcpy(p->d_items, it.data(), sizeof(int4) * it.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemset(p->d_work, 0, 2 * sizeof(unsigned)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        free_plan(p);
+        return fail(GK_EHIP, "upload of a many-grid plan failed");
+    }
+    out = p;
+    return GK_OK;
 }
 
 extern "C" {
@@ -660,6 +1114,8 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
     ALLOC(g->d_partials, sizeof(double) * (size_t)max_batch * MAX_BANDS);
     ALLOC(g->d_counters, sizeof(unsigned) * (size_t)max_batch);
     ALLOC(g->d_fbar, sizeof(float) * 4 * npix * (size_t)max_batch);
+    ALLOC(g->d_gpart, sizeof(double) * NCONST * MAX_BANDS_ADJ * (size_t)max_batch);
+    ALLOC(g->d_logdet, sizeof(double));
 #undef ALLOC
     {
         // compile-time tap counts of the stencil (register arrays up to 26 entries
@@ -680,6 +1136,18 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
         return fail(GK_EHIP, "upload of the stencil tables failed");
     }
     default_rules(g);
+    // adjoint bands: at most 40 x 40 pixels (pixel adjoints are staged in LDS)
+    g->adj_band_w = std::min(desc->nx, 40);
+    g->adj_band_h = std::min(desc->ny, 40);
+    while ((desc->nx + g->adj_band_w - 1) / g->adj_band_w * ((desc->ny + g->adj_band_h - 1) / g->adj_band_h) >
+           MAX_BANDS_ADJ) {
+        g->adj_band_w = std::min(desc->nx, g->adj_band_w + 8);
+        g->adj_band_h = std::min(desc->ny, g->adj_band_h + 8);
+    }
+    if (adj_lds_bytes(g->adj_band_h, g->adj_band_w, s, pad) > 64 * 1024) {
+        free_grid(g);
+        return fail(GK_EINVAL, "grid too large for the adjoint's LDS tiles in this build");
+    }
     *out = g;
     return GK_OK;
 }
@@ -687,6 +1155,7 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
 int destroy_grid(gk_grid_t g) {
     if (!g) return fail(GK_EINVAL, "grid is NULL");
     (void)hipDeviceSynchronize();
+    evict_plans(g);
     free_grid(g);
     return GK_OK;
 }
@@ -740,6 +1209,7 @@ int set_data(gk_grid_t g, const float* value, const float* err, int on_device, v
     HIPCHECK(hipMemcpyAsync(g->d_val, dv.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
     HIPCHECK(hipMemcpyAsync(g->d_ivar, iv.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
     HIPCHECK(hipMemcpyAsync(g->d_span, span.data(), ny * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(g->d_logdet, &logdet, sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHECK(hipStreamSynchronize(st));
     g->logdet = logdet;
     g->has_data = true;
@@ -788,8 +1258,144 @@ int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, doub
     if (rc) return rc;
     if (B > 0 && !grad) return fail(GK_EINVAL, "NULL grad");
     if (!g->has_data) return fail(GK_ESTATE, "loglike_grad_batch before set_data");
-    (void)stream;
-    return fail(GK_ESTATE, "gradient not available in this build");
+    if (B == 0) return GK_OK;
+    hipStream_t st = (hipStream_t)stream;
+    // pass 1: log-likelihood and d logL / d F at every pixel
+    int bh, bw;
+    choose_rule(g, B, bh, bw);
+    LaunchCfg c;
+    rc = make_cfg(g, bh, bw, c);
+    if (rc) return rc;
+    FwdArgs fa;
+    fill_args(g, c, fa, theta, stride);
+    fa.logL = logL;
+    fa.fbar = g->d_fbar;
+    hipError_t e = launch_fwd<MODE_FBAR>(g, c, fa, B, st);
+    if (e != hipSuccess) return fail(GK_EHIP, "forward (adjoint seed) launch failed: %s", hipGetErrorString(e));
+    // pass 2: adjoint of the PSF and of the model, chain rule to theta
+    AdjArgs aa;
+    aa.geo = g->geo;
+    aa.gw = g->d_gw;
+    aa.aof = g->d_aof;
+    aa.invW = g->invW;
+    aa.span = g->d_span;
+    aa.band_h = g->adj_band_h;
+    aa.band_w = g->adj_band_w;
+    aa.nbx = (g->d.nx + aa.band_w - 1) / aa.band_w;
+    aa.nbands = aa.nbx * ((g->d.ny + aa.band_h - 1) / aa.band_h);
+    aa.theta = theta;
+    aa.stride = stride;
+    aa.fbar = g->d_fbar;
+    aa.gpart = g->d_gpart;
+    aa.counters = g->d_counters;
+    aa.grad = grad;
+    const int lds = adj_lds_bytes(aa.band_h, aa.band_w, g->geo.s, g->geo.pad);
+    const dim3 grid2((unsigned)(B * aa.nbands)), block2(256);
+    const int bulge = g->d.bulge, nd = g->d.n_discs, halo = g->d.halo;
+    bool launched = false;
+#define GK_ALAUNCH(BU, ND, HA)                                                                  \
+    if (!launched && bulge == BU && nd == ND && halo == HA) {                                    \
+        hipLaunchKernelGGL((adj_kernel<BU, ND, HA>), grid2, block2, lds, st, aa);               \
+        launched = true;                                                                         \
+    }
+    GK_ALAUNCH(1, 0, 0) GK_ALAUNCH(1, 0, 1) GK_ALAUNCH(1, 0, 2)
+    GK_ALAUNCH(1, 1, 0) GK_ALAUNCH(1, 1, 1) GK_ALAUNCH(1, 1, 2)
+    GK_ALAUNCH(1, 2, 0) GK_ALAUNCH(1, 2, 1) GK_ALAUNCH(1, 2, 2)
+    GK_ALAUNCH(0, 1, 0) GK_ALAUNCH(0, 1, 1) GK_ALAUNCH(0, 1, 2)
+    GK_ALAUNCH(0, 2, 0) GK_ALAUNCH(0, 2, 1) GK_ALAUNCH(0, 2, 2)
+#undef GK_ALAUNCH
+    e = hipGetLastError();
+    if (!launched || e != hipSuccess)
+        return fail(GK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
+}
+
+int hmc_leapfrog(gk_grid_t g, double* theta, double* momentum, const double* inv_mass, double eps,
+                 int n_steps, int B, int stride, double* logL, double* grad, void* stream) {
+    int rc = check_call(g, theta, B, stride, logL);
+    if (rc) return rc;
+    if (B > 0 && (!momentum || !inv_mass || !grad)) return fail(GK_EINVAL, "NULL momentum, inv_mass or grad");
+    if (n_steps < 1) return fail(GK_EINVAL, "n_steps must be >= 1");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(GK_EINVAL, "eps must be finite and > 0");
+    if (!g->has_data) return fail(GK_ESTATE, "hmc_leapfrog before set_data");
+    if (B == 0) return GK_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = B * g->P;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    for (int k = 0; k <= n_steps; ++k) {
+        rc = loglike_grad_batch(g, theta, B, stride, logL, grad, stream);
+        if (rc) return rc;
+        const int stage = (k == 0) ? 0 : (k == n_steps ? 2 : 1);
+        hipLaunchKernelGGL(leapfrog_kernel, grid, block, 0, st, theta, momentum, grad, logL, inv_mass, eps,
+                           stage, B, g->P, stride);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(GK_EHIP, "leapfrog launch failed: %s", hipGetErrorString(e));
+    }
+    return GK_OK;
+}
+
+int loglike_multi(const gk_grid_t* grids, int n_gal, const double* theta, const int* theta_offset, int stride,
+                  double* logL, double* grad, void* stream) {
+    if (n_gal < 0) return fail(GK_EINVAL, "n_gal must be >= 0");
+    if (n_gal == 0) return GK_OK;
+    if (!grids || !theta_offset) return fail(GK_EINVAL, "NULL grids or theta_offset");
+    if (theta_offset[0] != 0) return fail(GK_EINVAL, "theta_offset[0] must be 0");
+    for (int i = 0; i < n_gal; ++i)
+        if (!grids[i]) return fail(GK_EINVAL, "grids[%d] is NULL", i);
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(GK_EHIP, "hipGetDevice failed");
+    for (int i = 0; i < n_gal; ++i) {
+        const gk_grid* g = grids[i];
+        const int rows = theta_offset[i + 1] - theta_offset[i];
+        if (rows < 0 || rows > g->max_batch)
+            return fail(GK_EINVAL, "galaxy %d has %d rows (max_batch %d)", i, rows, g->max_batch);
+        if (stride < g->P) return fail(GK_EINVAL, "stride %d < number of parameters %d of galaxy %d", stride, g->P, i);
+        if (!g->has_data) return fail(GK_ESTATE, "galaxy %d has no data (set_data)", i);
+        if (g->device != device) return fail(GK_EINVAL, "galaxy %d lives on device %d, not %d", i, g->device, device);
+        for (int k = 0; k < i; ++k)
+            if (grids[k] == g) return fail(GK_EINVAL, "grid of galaxy %d appears twice", i);
+    }
+    const int total = theta_offset[n_gal];
+    if (total == 0) return GK_OK;
+    if (!theta || !logL) return fail(GK_EINVAL, "NULL theta or logL");
+    hipStream_t st = (hipStream_t)stream;
+    if (grad) {
+        // gradient: one forward + adjoint launch pair per galaxy on the stream
+        for (int i = 0; i < n_gal; ++i) {
+            const int r0 = theta_offset[i], rows = theta_offset[i + 1] - r0;
+            if (rows == 0) continue;
+            int rc = loglike_grad_batch(grids[i], theta + (size_t)r0 * stride, rows, stride, logL + r0,
+                                        grad + (size_t)r0 * stride, stream);
+            if (rc) return rc;
+        }
+        return GK_OK;
+    }
+    MultiPlan* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        for (size_t k = 0; k < g_plans.size(); ++k)
+            if (plan_matches(g_plans[k], device, grids, n_gal, theta_offset)) {
+                p = g_plans[k];
+                g_plans.erase(g_plans.begin() + k);
+                g_plans.push_back(p);
+                break;
+            }
+        if (!p) {
+            int rc = build_plan(device, grids, n_gal, theta_offset, p);
+            if (rc) return rc;
+            if (g_plans.size() >= MAX_PLANS) {
+                (void)hipDeviceSynchronize();
+                free_plan(g_plans.front());
+                g_plans.erase(g_plans.begin());
+            }
+            g_plans.push_back(p);
+        }
+    }
+    hipLaunchKernelGGL(multi_kernel, dim3((unsigned)p->n_wg), dim3(MULTI_BS), p->lds, st, p->d_args, p->d_items,
+                       p->n_items, theta, stride, logL, p->d_work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GK_EHIP, "many-grid launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
 }
 
 }  // extern "C"

@@ -347,4 +347,173 @@ __device__ __forceinline__ void point_model(const TC& c, const Tabs& T, float du
     oLM = Bt * frcp(mass);
 }
 
+// ---------------------------------------------------------------------------
+// reverse mode of point_model: given the adjoints fb = d logL / d(B, v, sigma,
+// <L/M>) at one lattice point, accumulate d logL / d(constant) into ad[] for
+// the FP32 per-theta constants below (the chain rule to theta is applied
+// once per theta, in FP64).
+// ---------------------------------------------------------------------------
+enum {
+    C_UF = 0, C_VF, C_CA, C_SA, C_SEC2I,
+    C_INVRB, C_AB, C_CB, C_GMB, C_RB, C_MLB,
+    C_D0 = 11,          // per disc j: C_D0 + 7 j + {0 nl2Rd, 1 Ad, 2 inv2Rd, 3 Kd, 4 kf, 5 sf, 6 MLd}
+    C_H0 = 25, C_H1 = 26,
+    NCONST = 27
+};
+
+template <int BULGE, int NDISC, int HALO>
+__device__ __forceinline__ void point_model_adj(const TC& c, const Tabs& T, float du, float dv,
+                                                float fB, float fV, float fS, float fL,
+                                                float (&ad)[NCONST]) {
+    // ---- forward recomputation (as point_model), keeping what the reverse needs
+    const float xp = fmaf(du, c.ca, dv * c.sa);
+    const float yp = fmaf(dv, c.ca, -du * c.sa);
+    const float x2 = xp * xp, y2 = yp * yp;
+    const float r2 = fmaf(y2, c.sec2i, x2);
+    const float rinv = r2 > 0.0f ? frsq(r2) : 0.0f;
+    const float r = r2 * rinv;
+    const float cphi = xp * rinv;
+    float vc2 = 0.0f, Bt = 0.0f, BS = 0.0f, kB = 0.0f, sB = 0.0f, mass = 0.0f;
+    float scale = 1.0f;
+    float R = 0.0f, g = 0.0f, h = 0.0f, dg = 0.0f, dh = 0.0f, Bb = 0.0f, iqb = 0.0f;
+    bool clamped = true;
+    if (BULGE) {
+        R = fsqrt(x2 + y2);
+        const float sbr = R * c.invRb;
+        clamped = !(sbr > S_MIN);
+        const float sb = clamped ? S_MIN : sbr;
+        eval_gh_d(T.gh, sb, g, h, dg, dh);
+        Bb = c.Ab * g;
+        Bt = Bb;
+        BS = c.Cb * h;
+        mass = Bb * c.MLb;
+        iqb = frcp(r + c.Rb);
+        vc2 = c.GMb * r * iqb * iqb;
+    }
+    float eref = 0.0f;
+    if (!BULGE && NDISC > 0) {
+        eref = r * c.nl2Rd[0];
+        if (NDISC > 1) eref = fmaxf(eref, r * c.nl2Rd[1]);
+        scale = fexp2(eref);
+    }
+    float ex[2] = {0.0f, 0.0f}, Bd[2] = {0.0f, 0.0f}, ph[2] = {0.0f, 0.0f}, dph[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < NDISC; ++j) {
+        ex[j] = fexp2(fmaf(r, c.nl2Rd[j], -eref));
+        Bd[j] = c.Ad[j] * ex[j];
+        Bt += Bd[j];
+        kB = fmaf(Bd[j], c.kf[j], kB);
+        sB = fmaf(Bd[j], c.sf[j], sB);
+        mass = fmaf(Bd[j], c.MLd[j], mass);
+        ph[j] = eval_phi_d(T.phi, r * c.inv2Rd[j], dph[j]);
+        vc2 = fmaf(c.Kd[j], ph[j], vc2);
+    }
+    float mv = 0.0f, dmv = 0.0f, iqh = 0.0f;
+    if (HALO == 2) {
+        mv = eval_m_d(T.m, r * c.H0, dmv);
+        vc2 = fmaf(c.H1, mv, vc2);
+    } else if (HALO == 1) {
+        iqh = frcp(r + c.H0);
+        vc2 = fmaf(c.H1 * r, iqh * iqh, vc2);
+    }
+    const float vint = fsqrt(vc2);
+    const float ib = frcp(Bt);
+    const float S2 = fmaf(vc2, sB, BS) * ib;
+    const float oS = fsqrt(S2);
+    const float imass = frcp(mass);
+
+    // ---- reverse
+    float Btb = fB * scale;
+    // v = cphi vint kB ib
+    const float vkb = vint * kB * ib;
+    float cphib = fV * vkb;
+    float vintb = fV * cphi * kB * ib;
+    float kBb = fV * cphi * vint * ib;
+    float ibb = fV * cphi * vint * kB;
+    // sigma = sqrt(S2), S2 = (vc2 sB + BS) ib
+    const float S2b = oS > 0.0f ? fS * 0.5f * frcp(oS) : 0.0f;
+    float vc2b = S2b * sB * ib;
+    const float sBb = S2b * vc2 * ib;
+    const float BSb = S2b * ib;
+    ibb = fmaf(S2b, fmaf(vc2, sB, BS), ibb);
+    // <L/M> = Bt / mass
+    Btb = fmaf(fL, imass, Btb);
+    const float massb = -fL * Bt * imass * imass;
+    // ib = 1 / Bt
+    Btb = fmaf(-ibb, ib * ib, Btb);
+    // vint = sqrt(vc2)
+    if (vint > 0.0f) vc2b = fmaf(vintb, 0.5f * frcp(vint), vc2b);
+    float rb = 0.0f;
+    if (HALO == 2) {
+        ad[C_H1] = fmaf(vc2b, mv, ad[C_H1]);
+        const float xb = vc2b * c.H1 * dmv;
+        rb = fmaf(xb, c.H0, rb);
+        ad[C_H0] = fmaf(xb, r, ad[C_H0]);
+    } else if (HALO == 1) {
+        const float iq2 = iqh * iqh;
+        ad[C_H1] = fmaf(vc2b, r * iq2, ad[C_H1]);
+        // d/dr [r / q^2] = 1/q^2 - 2 r / q^3 ; d/dRh [r / q^2] = -2 r / q^3
+        const float t = vc2b * c.H1;
+        rb = fmaf(t, iq2 - 2.0f * r * iq2 * iqh, rb);
+        ad[C_H0] = fmaf(t, -2.0f * r * iq2 * iqh, ad[C_H0]);
+    }
+#pragma unroll
+    for (int j = 0; j < NDISC; ++j) {
+        const int o = C_D0 + 7 * j;
+        ad[o + 3] = fmaf(vc2b, ph[j], ad[o + 3]);
+        const float yb = vc2b * c.Kd[j] * dph[j];
+        rb = fmaf(yb, c.inv2Rd[j], rb);
+        ad[o + 2] = fmaf(yb, r, ad[o + 2]);
+        const float Bdb = fmaf(massb, c.MLd[j], fmaf(sBb, c.sf[j], fmaf(kBb, c.kf[j], Btb)));
+        ad[o + 6] = fmaf(massb, Bd[j], ad[o + 6]);
+        ad[o + 5] = fmaf(sBb, Bd[j], ad[o + 5]);
+        ad[o + 4] = fmaf(kBb, Bd[j], ad[o + 4]);
+        ad[o + 1] = fmaf(Bdb, ex[j], ad[o + 1]);
+        const float argb = Bdb * c.Ad[j] * ex[j] * 0.69314718f;
+        rb = fmaf(argb, c.nl2Rd[j], rb);
+        ad[o + 0] = fmaf(argb, r, ad[o + 0]);
+    }
+    float x2b = 0.0f, y2b = 0.0f;
+    if (BULGE) {
+        const float iq2 = iqb * iqb;
+        ad[C_GMB] = fmaf(vc2b, r * iq2, ad[C_GMB]);
+        const float t = vc2b * c.GMb;
+        rb = fmaf(t, iq2 - 2.0f * r * iq2 * iqb, rb);
+        ad[C_RB] = fmaf(t, -2.0f * r * iq2 * iqb, ad[C_RB]);
+        const float Bbb = fmaf(massb, c.MLb, Btb);
+        ad[C_MLB] = fmaf(massb, Bb, ad[C_MLB]);
+        ad[C_CB] = fmaf(BSb, h, ad[C_CB]);
+        ad[C_AB] = fmaf(Bbb, g, ad[C_AB]);
+        if (!clamped) {
+            const float sbb = fmaf(Bbb * c.Ab, dg, BSb * c.Cb * dh);
+            const float Rb_ = sbb * c.invRb;
+            ad[C_INVRB] = fmaf(sbb, R, ad[C_INVRB]);
+            if (R > 0.0f) {
+                const float t2 = Rb_ * 0.5f * frcp(R);
+                x2b += t2;
+                y2b += t2;
+            }
+        }
+    }
+    // frame: cphi = xp rinv, r = r2 rinv, rinv = r2^-1/2, r2 = y2 sec2i + x2
+    float xpb = cphib * rinv;
+    float r2b = 0.0f;
+    if (r2 > 0.0f) {
+        const float rinvb = fmaf(cphib, xp, rb * r2);
+        r2b = fmaf(rb, rinv, -0.5f * rinvb * rinv * rinv * rinv);
+    }
+    y2b = fmaf(r2b, c.sec2i, y2b);
+    ad[C_SEC2I] = fmaf(r2b, y2, ad[C_SEC2I]);
+    x2b += r2b;
+    xpb = fmaf(2.0f * xp, x2b, xpb);
+    const float ypb = 2.0f * yp * y2b;
+    // xp = du ca + dv sa, yp = dv ca - du sa, du = (u - Ui) - Uf
+    ad[C_CA] = fmaf(xpb, du, fmaf(ypb, dv, ad[C_CA]));
+    ad[C_SA] = fmaf(xpb, dv, fmaf(-ypb, du, ad[C_SA]));
+    const float dub = fmaf(xpb, c.ca, -ypb * c.sa);
+    const float dvb = fmaf(xpb, c.sa, ypb * c.ca);
+    ad[C_UF] -= dub;
+    ad[C_VF] -= dvb;
+}
+
 }  // namespace gk

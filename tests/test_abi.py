@@ -19,7 +19,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("create_grid", "set_data", "loglike_batch", "loglike_grad_batch", "eval_maps",
-              "n_params", "destroy_grid", "last_error"):
+              "n_params", "destroy_grid", "loglike_multi", "last_error"):
         assert n in names
 
 
@@ -54,6 +54,13 @@ def test_argument_errors_without_device():
     assert lib.set_data(None, None, None, 0, None) == gk.GK_EINVAL
     assert lib.destroy_grid(None) == gk.GK_EINVAL
     assert lib.set_launch_shape(None, 1, 1, 1) == gk.GK_EINVAL
+    assert lib.loglike_multi(None, -1, None, None, 13, None, None, None) == gk.GK_EINVAL
+    assert lib.loglike_multi(None, 0, None, None, 13, None, None, None) == gk.GK_OK
+    assert lib.loglike_multi(None, 2, None, None, 13, None, None, None) == gk.GK_EINVAL
+    nulls = (ctypes.c_void_p * 2)()
+    offs = (ctypes.c_int * 3)(0, 1, 2)
+    assert lib.loglike_multi(nulls, 2, None, offs, 13, None, None, None) == gk.GK_EINVAL
+    assert "NULL" in gk.last_error()
 
 
 def test_binding_has_no_cpu_fallback():

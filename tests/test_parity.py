@@ -178,3 +178,143 @@ def test_errors_on_device(gk):
     with pytest.raises(ValueError):
         grid.loglike(torch.zeros(2, spec.n_params - 1, dtype=torch.float64, device="cuda"))
     grid.close()
+
+
+# --- gradient (hand-written adjoint) -------------------------------------------
+GRAD_RTOL, GRAD_NORM_TOL = 1e-3, 1e-4
+
+
+def check_grad(got, ref, tag):
+    tol = GRAD_RTOL * np.abs(ref) + GRAD_NORM_TOL * np.linalg.norm(ref)
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), f"{tag}: params {np.nonzero(bad)[0]}: gpu {got[bad]} oracle {ref[bad]}"
+    return float(np.max(np.abs(got - ref) / (np.abs(ref) + np.linalg.norm(ref))))
+
+
+@pytest.mark.parametrize("name,n", [("tiny", 4), ("ragged_s3_2d_hq", 3), ("nobulge_1d", 3),
+                                    ("nobulge_2d_nohalo", 3), ("bulge_only_s5", 3), ("no_psf", 3),
+                                    ("realistic", 2)])
+def test_gradient_matches_oracle(gk, name, n):
+    spec, data, err, thetas = make_case(name)
+    thetas = thetas[:n]
+    say(f"[grad] case={name} B={n} P={spec.n_params}")
+    grid = gk.Grid(spec, max_batch=16)
+    grid.set_data(data, err)
+    th = torch.tensor(thetas, dtype=torch.float64, device="cuda")
+    lg, g = grid.loglike_grad(th)
+    ll = grid.loglike(th)
+    assert torch.equal(lg, ll), "log-likelihood of the gradient call differs from loglike_batch"
+    g = g.cpu().numpy()
+    worst = 0.0
+    for k, t in enumerate(thetas):
+        ref = M.grad_complex_step(spec, data, err, t)
+        worst = max(worst, check_grad(g[k], ref, f"{name}[{k}]"))
+    say(f"  worst relative gradient error {worst:.2e}")
+    grid.close()
+
+
+def test_gradient_invalid_rows_and_padding(gk):
+    spec, data, err, thetas = make_case("tiny")
+    grid = gk.Grid(spec, max_batch=16)
+    grid.set_data(data, err)
+    th = torch.zeros(3, spec.n_params + 3, dtype=torch.float64, device="cuda")
+    th[:, :spec.n_params] = torch.tensor(thetas[:3])
+    th[1, W.param_names(spec).index("Rb")] = -1.0
+    out = torch.empty(3, dtype=torch.float64, device="cuda")
+    grad = torch.full((3, spec.n_params + 3), 7.0, dtype=torch.float64, device="cuda")
+    gk.loglike_grad_batch(grid.handle, th, out, grad)
+    grad = grad.cpu()
+    assert torch.all(grad[1] == 0.0) and torch.isinf(out[1]).item()
+    assert torch.all(grad[:, spec.n_params:] == 0.0)
+    ref = M.grad_complex_step(spec, data, err, thetas[0])
+    check_grad(grad[0, :spec.n_params].numpy(), ref, "padded stride")
+    grid.close()
+
+
+def test_autograd_function(gk):
+    spec, data, err, thetas = make_case("ragged_s3_2d_hq")
+    grid = gk.Grid(spec, max_batch=8)
+    grid.set_data(data, err)
+    th = torch.tensor(thetas[:3], dtype=torch.float64, device="cuda", requires_grad=True)
+    w = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda")
+    (gk.LogLike.apply(th, grid) * w).sum().backward()
+    _, g = grid.loglike_grad(th.detach())
+    torch.testing.assert_close(th.grad, w[:, None] * g, rtol=0, atol=0)
+    grid.close()
+
+
+# --- HMC trajectory and HIP-graph capture ---------------------------------------
+def _hmc_setup(gk, B=4):
+    spec, data, err, thetas = make_case("ragged_s3_2d_hq")
+    grid = gk.Grid(spec, max_batch=16)
+    grid.set_data(data, err)
+    P = spec.n_params
+    th = torch.tensor(np.repeat(thetas[:1], B, axis=0), dtype=torch.float64, device="cuda")
+    th += 1e-3 * torch.randn(th.shape, dtype=torch.float64, device="cuda",
+                             generator=torch.Generator("cuda").manual_seed(5))
+    # unit-ish scales: a diagonal mass from the curvature scale of each parameter
+    scale = torch.tensor([0.05, 0.05, 0.5, 0.5, 0.01, 0.01, 0.01] + [0.01, 0.01, 0.01, 0.01] * 2
+                         + [0.01, 0.1], dtype=torch.float64, device="cuda")[:P]
+    inv_mass = scale ** 2
+    mom = torch.randn(th.shape, dtype=torch.float64, device="cuda",
+                      generator=torch.Generator("cuda").manual_seed(6)) / scale
+    return grid, spec, th, mom, inv_mass
+
+
+def test_hmc_energy_and_reversibility(gk):
+    grid, spec, th, mom, inv_mass = _hmc_setup(gk)
+    say("[hmc] leapfrog trajectory on ragged_s3_2d_hq")
+    B, P = th.shape
+    logL0 = grid.loglike(th)
+    H0 = -logL0 + 0.5 * (mom ** 2 * inv_mass).sum(1)
+    th1, mom1 = th.clone(), mom.clone()
+    logL = torch.empty(B, dtype=torch.float64, device="cuda")
+    grad = torch.empty(B, P, dtype=torch.float64, device="cuda")
+    eps, n = 2e-3, 8
+    gk.hmc_leapfrog(grid.handle, th1, mom1, inv_mass, eps, n, logL, grad)
+    H1 = -logL + 0.5 * (mom1 ** 2 * inv_mass).sum(1)
+    torch.testing.assert_close(logL, grid.loglike(th1), rtol=0, atol=0)
+    dH = (H1 - H0).abs().max().item()
+    say(f"  max |dH| = {dH:.3e} over {n} steps (|H| ~ {H0.abs().max().item():.3e})")
+    assert dH < 1.0, dH
+    # reversibility: flip the momentum and integrate back
+    th2, mom2 = th1.clone(), -mom1.clone()
+    gk.hmc_leapfrog(grid.handle, th2, mom2, inv_mass, eps, n, logL, grad)
+    torch.testing.assert_close(th2, th, rtol=0, atol=1e-6)
+    grid.close()
+
+
+def test_hmc_graph_capture_replays(gk):
+    grid, spec, th, mom, inv_mass = _hmc_setup(gk)
+    say("[hmc] HIP-graph capture of one trajectory")
+    B, P = th.shape
+    logL = torch.empty(B, dtype=torch.float64, device="cuda")
+    grad = torch.empty(B, P, dtype=torch.float64, device="cuda")
+    th_s, mom_s = th.clone(), mom.clone()
+    # eager reference: three trajectories in a row
+    ref = []
+    te, me = th.clone(), mom.clone()
+    for _ in range(3):
+        gk.hmc_leapfrog(grid.handle, te, me, inv_mass, 1e-3, 4, logL, grad)
+        ref.append((te.clone(), logL.clone()))
+    # captured: the same calls replayed from a graph, with eager work between replays
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gk.hmc_leapfrog(grid.handle, th.clone(), mom.clone(), inv_mass, 1e-3, 4, logL, grad)
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gk.hmc_leapfrog(grid.handle, th_s, mom_s, inv_mass, 1e-3, 4, logL, grad)
+    th_s.copy_(th)
+    mom_s.copy_(mom)
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(th_s, ref[k][0]), k
+        assert torch.equal(logL, ref[k][1]), k
+        grid.loglike(th_s[:1])        # eager work between replays
+        torch.cuda.synchronize()
+    del g
+    grid.close()
