@@ -108,12 +108,26 @@ def _oracle_worker(args):
     return out, time.perf_counter() - t0
 
 
+def _oracle_items_worker(items):
+    """items: list of (spec dict, data, err, theta); returns (values, CPU seconds)."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import workloads as W
+    from oracle import model as M
+    t0 = time.perf_counter()
+    out = [M.loglike(W.GridSpec(**sd), d, e, t) for sd, d, e, t in items]
+    return out, time.perf_counter() - t0
+
+
+def _host_cores() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                      else os.cpu_count() or 1))
+
+
 def cpu_baseline(spec, data, err, thetas, budget_s: float = 20.0):
     import dataclasses
     from concurrent.futures import ProcessPoolExecutor
     import multiprocessing as mp
-    cores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
-                       else os.cpu_count() or 1))
+    cores = _host_cores()
     spec_d = dataclasses.asdict(spec)
     # calibrate on one vector in this process, then size the sample to ~budget_s of CPU work
     sys.path.insert(0, ROOT)
@@ -141,12 +155,180 @@ def cpu_baseline(spec, data, err, thetas, budget_s: float = 20.0):
 
 
 # ----------------------------------------------------------------------------
+# many galaxies in one launch (loglike_multi)
+# ----------------------------------------------------------------------------
+def bench_uneven(args):
+    import dataclasses
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    import torch
+    import workloads as W
+    import paper_2205_06819_amd as gk
+
+    wls = W.uneven_galaxies()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stride = max(w.spec.n_params for w in wls)
+    grids, datas, rows = [], [], []
+    for w in wls:
+        rng = np.random.default_rng(w.seed)
+        g = gk.Grid(w.spec, max_batch=w.batch)
+        truth = W.draw_thetas(w.spec, 1, rng)
+        maps = g.maps(torch.tensor(truth, dtype=torch.float64, device=dev))[0].cpu().numpy()
+        mask = w.mask()
+        err = W.error_maps(maps, mask)
+        data = W.noisy_data(maps, err, rng)
+        g.set_data(data, err)
+        th = np.zeros((w.batch, stride))
+        th[:, :w.spec.n_params] = W.draw_thetas(w.spec, w.batch, rng)
+        grids.append(g)
+        datas.append((data, err, mask))
+        rows.append(th)
+    offs = np.concatenate([[0], np.cumsum([w.batch for w in wls])]).astype(np.int32)
+    th = torch.tensor(np.vstack(rows), device=dev)
+    total = int(offs[-1])
+    out = torch.empty(total, dtype=torch.float64, device=dev)
+    handles = [g.handle for g in grids]
+    stream = torch.cuda.current_stream()
+    tuned = None
+    if not args.no_tune:
+        from paper_2205_06819_amd import autotune
+        tuned = autotune.tune_multi(grids, th, offs, reps=2)
+    gk.loglike_multi(handles, th, offs, out)              # builds the work plan
+    for _ in range(args.warmup):
+        gk.loglike_multi(handles, th, offs, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        gk.loglike_multi(handles, th, offs, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    evals = total / (ms_step * 1e-3)
+    multi_vals = out.cpu().numpy()
+    # the same work as one launch per galaxy
+    outs = [out[offs[k]:offs[k + 1]] for k in range(len(wls))]
+    ths = [th[offs[k]:offs[k + 1], :wls[k].spec.n_params].contiguous() for k in range(len(wls))]
+    for k, g in enumerate(grids):
+        g.loglike(ths[k], outs[k])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    reps = max(1, args.steps // 4)
+    for _ in range(reps):
+        for k, g in enumerate(grids):
+            g.loglike(ths[k], outs[k])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    per_grid_evals = reps * total / (e0.elapsed_time(e1) * 1e-3)
+    assert np.allclose(out.cpu().numpy(), multi_vals, rtol=1e-9, atol=1e-6)
+
+    flop = 0
+    for w, (_, _, mask), r in zip(wls, datas, rows):
+        flop += len(r) * (needed_points(w.spec, mask) * flops_per_point(w.spec)
+                          + int(mask.sum()) * flops_per_pixel(w.spec))
+    achieved = flop / (ms_step * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "frac_of_nonpacked_fp32": round(achieved / PEAK_FP32_NONPACKED, 4),
+            "kernel": "gk::multi_kernel", "flop_per_step": flop}
+
+    cpu = None
+    if not args.no_cpu:
+        cores = _host_cores()
+        items, idx = [], []
+        t_est = 0.0
+        from oracle import model as M
+        k = 0
+        while t_est < args.cpu_budget * cores and k < 4 * len(wls):
+            gi, ri = k % len(wls), k // len(wls)
+            w = wls[gi]
+            data, err, _ = datas[gi]
+            items.append((dataclasses.asdict(w.spec), data.astype(np.float32).astype(np.float64),
+                          err.astype(np.float32).astype(np.float64), rows[gi][ri, :w.spec.n_params]))
+            idx.append(int(offs[gi]) + ri)
+            t_est += 0.07 * (w.spec.nx * w.spec.ny) / 6400.0 * (w.spec.n_params / 17.0) * 3
+            k += 1
+        chunks = [items[i::cores] for i in range(cores)]
+        t0 = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+            res = list(ex.map(_oracle_items_worker, chunks))
+        wall = time.perf_counter() - t0
+        vals = np.array([res[i % cores][0][i // cores] for i in range(len(items))])
+        work = sum(r[1] for r in res)
+        rel = np.abs(vals - multi_vals[idx]) / np.maximum(1.0, np.abs(vals))
+        cpu = {"value": round(len(items) / wall, 3), "unit": "likelihood evals/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{len(items)} (galaxy, parameter vector) pairs, galaxies in order, "
+                         f"{cores} worker processes, {work:.1f} s CPU in {wall:.1f} s wall",
+               "max_rel_diff_vs_gpu": float(rel.max())}
+    line = {
+        "metric": "likelihood evals/s and gradient evals/s (params×spaxels/s), batched vs plain",
+        "value": round(evals, 1), "unit": "likelihood evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256 galaxies, square grids of side U{30..120}, 2-4 components, "
+                               "3x3 supersampling, PSF FWHM 2.5 px, 128 parameter vectors each, "
+                               "one launch", "batch": total, "galaxies": len(wls),
+                   "band_policy": list(tuned[:2]) if tuned else None},
+        "one_launch_per_galaxy_evals_per_s": round(per_grid_evals, 1),
+        "speedup_vs_launch_per_galaxy": round(evals / per_grid_evals, 3),
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    for g in grids:
+        g.close()
+
+
+def time_hmc(gk, grid, th, n_steps: int, eps: float = 1e-4) -> dict:
+    """One leapfrog trajectory of n_steps for every row, captured once in a
+    HIP graph and replayed from the same start (restored outside the timing)."""
+    import torch
+    B, P = th.shape
+    dev = th.device
+    g = torch.Generator(device="cpu").manual_seed(5)
+    mom0 = torch.randn(B, P, generator=g, dtype=torch.float64).to(dev)
+    theta, mom = th.clone(), mom0.clone()
+    inv_mass = torch.ones(P, dtype=torch.float64, device=dev)
+    logL = torch.empty(B, dtype=torch.float64, device=dev)
+    grad = torch.empty(B, P, dtype=torch.float64, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gk.hmc_leapfrog(grid.handle, theta, mom, inv_mass, eps, n_steps, logL, grad)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gk.hmc_leapfrog(grid.handle, theta, mom, inv_mass, eps, n_steps, logL, grad)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(2):
+        theta.copy_(th)
+        mom.copy_(mom0)
+        torch.cuda.synchronize()
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    frozen = int((~torch.isfinite(logL)).sum())
+    del graph
+    ms = min(times)
+    return {"hmc_steps": n_steps, "ms_per_hmc_trajectory": ms,
+            "hmc_grad_evals_per_s": B * (n_steps + 1) / (ms * 1e-3), "hmc_rows_frozen": frozen}
+
+
+# ----------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="realistic")
+    ap.add_argument("--workload", default="realistic",
+                    help="realistic (default), tiny, adjoint, stress or uneven (many galaxies)")
+    ap.add_argument("--hmc-steps", type=int, default=0,
+                    help="also time one graph-captured leapfrog trajectory of this many steps")
     ap.add_argument("--plain", type=int, default=256, help="number of single-vector calls timed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
@@ -160,6 +342,9 @@ def main():
               "(every (galaxy, parameter vector) pair is independent; see the design notes "
               "on sharding). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "uneven":
+        return bench_uneven(args)
 
     import torch
     import workloads as W
@@ -223,6 +408,8 @@ def main():
             torch.cuda.synchronize()
             ms_grad = e0.elapsed_time(e1) / args.steps
             grad_info = {"grad_evals_per_s": B / (ms_grad * 1e-3), "ms_per_grad_step": ms_grad}
+            if args.hmc_steps > 0:
+                grad_info.update(time_hmc(gk, grid, th, args.hmc_steps))
 
     # ---- plain form: one call (one launch sequence) per parameter vector
     n_plain = min(args.plain, B)
@@ -319,7 +506,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "batch": B,
                    "spaxels": spax, "valid_spaxels": n_valid, "params": P,
                    "supersample": spec.supersample, "psf_sigma_px": round(spec.psf_sigma_px, 5),
-                   "launch_shape": list(tuned[:2]) if tuned else None},
+                   "launch_shape": list(tuned[:3]) if tuned else None},
         "params_x_spaxels_per_s": round(evals * P * spax, 1),
         "plain_evals_per_s": round(plain_evals, 1),
         "plain_host_loop_evals_per_s": round(plain_loop_evals, 1),

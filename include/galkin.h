@@ -134,8 +134,8 @@ int hmc_leapfrog(gk_grid_t grid, double* theta, double* momentum, const double* 
  * = 0, non-decreasing; rows theta_offset[g] .. theta_offset[g+1]-1 of theta
  * (device float64 [rows][stride], stride >= every grid's P) belong to galaxy g
  * and number at most that grid's max_batch; logL: device float64 [rows].
- * Workgroups take (galaxy, row, pixel band) items from a device queue in
- * decreasing cost order.  The first call with a given (grids, theta_offset,
+ * Each workgroup evaluates one (galaxy, row, pixel band) item; items are
+ * dispatched in decreasing cost order.  The first call with a given (grids, theta_offset,
  * launch shapes) builds and uploads that work plan (allocating and
  * synchronising); repeated calls with the same arguments only enqueue the
  * launch and may then be captured in a HIP graph.  A destroyed grid's plans
@@ -146,9 +146,13 @@ int hmc_leapfrog(gk_grid_t grid, double* theta, double* momentum, const double* 
 int loglike_multi(const gk_grid_t* grids, int n_gal, const double* theta, const int* theta_offset,
                   int stride, double* logL, double* grad, void* hip_stream);
 
-/* Launch shape used for batches of size >= batch_min (band of band_h x band_w
- * pixels per workgroup; the autotuner sets these).  band_h, band_w >= 1. */
-int set_launch_shape(gk_grid_t grid, int batch_min, int band_h, int band_w);
+/* Launch shape used for batches of size >= batch_min: a band of band_h x
+ * band_w pixels per workgroup (band_h, band_w >= 1) and steps pixel rows per
+ * model phase (1..4; 0 = chosen from the lattice factor).  The autotuner sets
+ * these.  GK_EINVAL if the shape does not fit the kernel's limits (band_w <=
+ * 128, at most 1024 bands, LDS).  Also used by loglike_multi (band_w capped at
+ * 64 there). */
+int set_launch_shape(gk_grid_t grid, int batch_min, int band_h, int band_w, int steps);
 
 /* Message describing the last error returned on the calling thread. */
 const char* last_error(void);

@@ -58,7 +58,7 @@ def _load() -> ctypes.CDLL:
     lib.loglike_batch.argtypes = [vp, vp, i, i, vp, vp]
     lib.loglike_grad_batch.argtypes = [vp, vp, i, i, vp, vp, vp]
     lib.eval_maps.argtypes = [vp, vp, i, i, vp, vp]
-    lib.set_launch_shape.argtypes = [vp, i, i, i]
+    lib.set_launch_shape.argtypes = [vp, i, i, i, i]
     lib.hmc_leapfrog.argtypes = [vp, vp, vp, vp, d, i, i, i, vp, vp, vp]
     lib.loglike_multi.argtypes = [vp, i, vp, vp, i, vp, vp, vp]
     lib.last_error.restype = ctypes.c_char_p
@@ -210,8 +210,8 @@ def loglike_multi(handles, theta: torch.Tensor, theta_offset, out: Optional[torc
     return out
 
 
-def set_launch_shape(handle: int, batch_min: int, band_h: int, band_w: int) -> None:
-    _check(_lib.set_launch_shape(handle, int(batch_min), int(band_h), int(band_w)))
+def set_launch_shape(handle: int, batch_min: int, band_h: int, band_w: int, steps: int = 0) -> None:
+    _check(_lib.set_launch_shape(handle, int(batch_min), int(band_h), int(band_w), int(steps)))
 
 
 def last_error() -> str:
@@ -252,8 +252,8 @@ class Grid:
     def maps(self, theta, out=None, stream=None):
         return eval_maps(self.handle, theta, self.ny, self.nx, out, stream)
 
-    def set_launch_shape(self, batch_min, band_h, band_w):
-        set_launch_shape(self.handle, batch_min, band_h, band_w)
+    def set_launch_shape(self, batch_min, band_h, band_w, steps=0):
+        set_launch_shape(self.handle, batch_min, band_h, band_w, steps)
 
 
 class LogLike(torch.autograd.Function):

@@ -55,9 +55,11 @@ def _time(grid: Grid, th: torch.Tensor, out: torch.Tensor, reps: int) -> float:
 
 
 def tune(grid: Grid, th: torch.Tensor, reps: int = 3, use_cache: bool = True,
-         shapes: Optional[List[Tuple[int, int]]] = None) -> Tuple[int, int, float]:
-    """Pick the fastest band shape for batches of th.shape[0] vectors and install
-    it for batch sizes >= that B.  Returns (band_h, band_w, ms)."""
+         shapes: Optional[List[Tuple[int, int]]] = None) -> Tuple[int, int, int, float]:
+    """Pick the fastest band shape and pixel rows per model phase for batches of
+    th.shape[0] vectors and install it for batch sizes >= that B.  Band shapes
+    are timed with the automatic row count, then the three best shapes with
+    every row count.  Returns (band_h, band_w, steps, ms)."""
     B = th.shape[0]
     key = _key(grid, B)
     cache: Dict[str, list] = {}
@@ -66,25 +68,80 @@ def tune(grid: Grid, th: torch.Tensor, reps: int = 3, use_cache: bool = True,
             cache = json.load(open(CACHE))
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache:
-        h, w, ms = cache[key]
-        grid.set_launch_shape(B, h, w)
-        return h, w, ms
+    if use_cache and key in cache and len(cache[key]) == 4:
+        h, w, st, ms = cache[key]
+        grid.set_launch_shape(B, h, w, st)
+        return h, w, st, ms
     out = torch.empty(B, dtype=torch.float64, device=th.device)
-    best = None
+    timed = []
     for (h, w) in (shapes or candidates(grid.nx, grid.ny, B)):
         try:
-            grid.set_launch_shape(B, h, w)
+            grid.set_launch_shape(B, h, w, 0)
         except GalkinError:
             continue
-        ms = _time(grid, th, out, reps)
-        if best is None or ms < best[2]:
-            best = (h, w, ms)
-    grid.set_launch_shape(B, best[0], best[1])
+        timed.append((_time(grid, th, out, reps), h, w, 0))
+    if not timed:
+        raise GalkinError(-1, "no launch shape fits this grid")
+    timed.sort()
+    best = timed[0]
+    for (_, h, w, _) in timed[:3]:
+        for st in (1, 2, 3, 4):
+            try:
+                grid.set_launch_shape(B, h, w, st)
+            except GalkinError:
+                continue
+            ms = _time(grid, th, out, reps)
+            if ms < best[0]:
+                best = (ms, h, w, st)
+    ms, h, w, st = best
+    grid.set_launch_shape(B, h, w, st)
     if use_cache:
-        cache[key] = list(best)
+        cache[key] = [h, w, st, ms]
         try:
             json.dump(cache, open(CACHE, "w"), indent=1)
         except OSError:
             pass
+    return h, w, st, ms
+
+
+def multi_policies(n_x: int, n_y: int) -> List[Tuple[int, int]]:
+    """Band shapes tried for one grid of a many-grid launch (band_w <= 64)."""
+    w = min(n_x, 64)
+    if n_x > 64:
+        w = (n_x + 1) // 2 if (n_x + 1) // 2 <= 64 else 64
+    return [(n_y, w), (min(n_y, 32), w), (min(n_y, 16), w), (min(n_y, 8), w)]
+
+
+def tune_multi(grids: List[Grid], th: torch.Tensor, offsets, reps: int = 3) -> Tuple[int, int, float]:
+    """Pick one band policy (index into multi_policies) and row count for all
+    grids of a many-grid launch by timing the whole launch; installs it on
+    every grid for its own row count.  Returns (policy, steps, ms)."""
+    from . import loglike_multi
+    handles = [g.handle for g in grids]
+    rows = [int(offsets[k + 1]) - int(offsets[k]) for k in range(len(grids))]
+    out = torch.empty(int(offsets[-1]), dtype=torch.float64, device=th.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for pol in range(4):
+        for st in (0, 1, 2):
+            try:
+                for g, r in zip(grids, rows):
+                    h, w = multi_policies(g.nx, g.ny)[pol]
+                    g.set_launch_shape(max(1, r), h, w, st)
+                loglike_multi(handles, th, offsets, out)
+            except GalkinError:
+                continue
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                loglike_multi(handles, th, offsets, out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            if best is None or ms < best[2]:
+                best = (pol, st, ms)
+    pol, st, ms = best
+    for g, r in zip(grids, rows):
+        h, w = multi_policies(g.nx, g.ny)[pol]
+        g.set_launch_shape(max(1, r), h, w, st)
     return best

@@ -395,70 +395,40 @@ __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
 }
 
 // ============================================================================
-// many grids in one persistent launch: workgroups take work items (grid,
-// parameter row within the grid, band, first row of the grid in the batch)
-// from an atomic queue; the host orders the items by decreasing cost
+// many grids in one launch: workgroup i takes work item i (grid, parameter row
+// within the grid, band, first row of the grid in the batch); the host orders
+// the items by decreasing cost, so the dispatcher hands out the longest items
+// first and the short ones fill the tail.  (A persistent loop over an atomic
+// queue kept loop-invariant state live across items: 206 instead of 125 VGPRs,
+// half the occupancy, and slower overall.)
 // ============================================================================
 typedef const __attribute__((address_space(4))) int* const_word_ptr;
 
 constexpr int MULTI_BS = 256;   // threads per workgroup of the many-grid launch
 
-__global__ void __launch_bounds__(MULTI_BS) __attribute__((amdgpu_waves_per_eu(2)))
-multi_kernel(const FwdArgs* __restrict__ grids,
-                                                    const int4* __restrict__ items, int n_items,
-                                                    const double* theta, int stride, double* logL,
-                                                    unsigned* work) {
+__global__ void __launch_bounds__(MULTI_BS) multi_kernel(const FwdArgs* __restrict__ grids,
+                                                         const int4* __restrict__ items,
+                                                         const double* theta, int stride, double* logL) {
     extern __shared__ __align__(16) float smem[];
-    __shared__ int s_item;
-    const int tid = threadIdx.x, BS = blockDim.x;
-    for (int i = tid; i < TAB_GH; i += BS) smem[i] = gk_tab_gh[i];
-    for (int i = tid; i < TAB_PHI; i += BS) smem[TAB_GH + i] = gk_tab_phi[i];
-    for (int i = tid; i < TAB_M; i += BS) smem[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) s_item = (int)__hip_atomic_fetch_add(work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int it = uni(s_item);
-        if (it >= n_items) break;
-        const_word_ptr iw = (const_word_ptr)(items) + 4 * it;
-        const int g = iw[0], row = iw[1], band = iw[2], off = iw[3];
-        // this grid's parameters, word by word through scalar loads
-        union {
-            FwdArgs a;
-            int w[sizeof(FwdArgs) / 4];
-        } u;
-        {
-            constexpr int NW = (int)(sizeof(FwdArgs) / 4);
-            const_word_ptr src = (const_word_ptr)(grids) + (size_t)g * NW;
-#pragma unroll
-            for (int k = 0; k < NW; ++k) u.w[k] = src[k];
-        }
-        FwdArgs& a = u.a;
-        a.theta = theta + (size_t)off * stride;   // this grid's rows start at row off
-        a.stride = stride;
-        a.logL = logL + off;
-        const int comp = a.geo.bulge * 100 + a.geo.ndisc * 10 + a.geo.halo;
-        switch (comp) {
+    const_word_ptr iw = (const_word_ptr)(items) + 4 * blockIdx.x;
+    const int g = iw[0], row = iw[1], band = iw[2], off = iw[3];
+    FwdArgs a = grids[g];
+    a.theta = theta + (size_t)off * stride;   // this grid's rows start at row off
+    a.stride = stride;
+    a.logL = logL + off;
+    const int comp = a.geo.bulge * 100 + a.geo.ndisc * 10 + a.geo.halo;
+    switch (comp) {
 #define GK_MCASE(BU, ND, HA)                                                                   \
     case BU * 100 + ND * 10 + HA:                                                              \
-        fwd_band<BU, ND, HA, MODE_LOGL>(a, row, band, smem, false);                             \
+        fwd_band<BU, ND, HA, MODE_LOGL>(a, row, band, smem, true);                              \
         break;
-            GK_MCASE(1, 0, 0) GK_MCASE(1, 0, 1) GK_MCASE(1, 0, 2)
-            GK_MCASE(1, 1, 0) GK_MCASE(1, 1, 1) GK_MCASE(1, 1, 2)
-            GK_MCASE(1, 2, 0) GK_MCASE(1, 2, 1) GK_MCASE(1, 2, 2)
-            GK_MCASE(0, 1, 0) GK_MCASE(0, 1, 1) GK_MCASE(0, 1, 2)
-            GK_MCASE(0, 2, 0) GK_MCASE(0, 2, 1) GK_MCASE(0, 2, 2)
+        GK_MCASE(1, 0, 0) GK_MCASE(1, 0, 1) GK_MCASE(1, 0, 2)
+        GK_MCASE(1, 1, 0) GK_MCASE(1, 1, 1) GK_MCASE(1, 1, 2)
+        GK_MCASE(1, 2, 0) GK_MCASE(1, 2, 1) GK_MCASE(1, 2, 2)
+        GK_MCASE(0, 1, 0) GK_MCASE(0, 1, 1) GK_MCASE(0, 1, 2)
+        GK_MCASE(0, 2, 0) GK_MCASE(0, 2, 1) GK_MCASE(0, 2, 2)
 #undef GK_MCASE
-            default: break;
-        }
-    }
-    // the last workgroup out re-arms the queue for the next launch
-    if (tid == 0) {
-        const unsigned out = __hip_atomic_fetch_add(work + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (out == gridDim.x - 1) {
-            __hip_atomic_store(work, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(work + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        default: break;
     }
 }
 
@@ -734,7 +704,7 @@ static int fail(int code, const char* fmt, ...) {
     } while (0)
 
 struct LaunchRule {
-    int batch_min, band_h, band_w;
+    int batch_min, band_h, band_w, steps;   // steps: pixel rows per model phase, 0 = automatic
 };
 
 struct gk_grid {
@@ -788,28 +758,45 @@ static void free_grid(gk_grid* g) {
     delete g;
 }
 
-static int choose_rule(const gk_grid* g, int B, int& bh, int& bw) {
+static int choose_rule(const gk_grid* g, int B, int& bh, int& bw, int& steps) {
     bh = g->d.ny;
     bw = g->d.nx;
+    steps = 0;
     int best = -1;
     for (const auto& r : g->rules)
-        if (r.batch_min <= B && r.batch_min > best) { best = r.batch_min; bh = r.band_h; bw = r.band_w; }
+        if (r.batch_min <= B && r.batch_min > best) {
+            best = r.batch_min;
+            bh = r.band_h;
+            bw = r.band_w;
+            steps = r.steps;
+        }
     bh = std::min(bh, g->d.ny);
     bw = std::min(bw, g->d.nx);
     return GK_OK;
 }
 
+struct LaunchCfg;
+static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int bs_fixed = 0, int steps = 0);
+
+// Narrow (then shorten) a band until its launch fits the LDS and band limits.
+static void fit_shape(const gk_grid* g, int& bh, int& bw, int bs_fixed);
+
 static int default_rules(gk_grid* g) {
     // Large batches: whole frames (up to 128 pixels wide) per workgroup.  Small
     // batches: small square bands so that one theta spreads over many CUs.
     const int nx = g->d.nx, ny = g->d.ny;
-    const int bw = std::min(nx, 128);
     g->rules.clear();
-    g->rules.push_back({512, ny, bw});
+    int bh = ny, bw = std::min(nx, 128);
+    fit_shape(g, bh, bw, 0);
+    g->rules.push_back({512, bh, bw, 0});
     int side = std::max(4, (int)std::ceil(std::sqrt((double)nx * ny / 64.0)));
-    g->rules.push_back({1, std::min(ny, side), std::min(nx, side)});
+    bh = std::min(ny, side), bw = std::min(nx, side);
+    fit_shape(g, bh, bw, 0);
+    g->rules.push_back({1, bh, bw, 0});
     int mid = std::max(8, (int)std::ceil(std::sqrt((double)nx * ny / 8.0)));
-    g->rules.push_back({32, std::min(ny, mid), std::min(nx, std::max(mid, 16))});
+    bh = std::min(ny, mid), bw = std::min(nx, std::max(mid, 16));
+    fit_shape(g, bh, bw, 0);
+    g->rules.push_back({32, bh, bw, 0});
     return GK_OK;
 }
 
@@ -817,7 +804,7 @@ struct LaunchCfg {
     int band_h, band_w, nbx, nbands, BS, gsub, xw, lds;
 };
 
-static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int bs_fixed = 0) {
+static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int bs_fixed, int steps) {
     const int s = g->geo.s, pad = g->geo.pad;
     c.band_h = band_h;
     c.band_w = band_w;
@@ -832,16 +819,29 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int 
         c.BS = bs_fixed;
     }
     c.xw = band_w * s + 2 * pad + 1;
-    // pixel-row steps per model phase: about four lattice points per thread,
-    // at most RS_CAP lattice rows, and the row buffer within ~40 KiB of LDS
+    // pixel-row steps per model phase: about six lattice rows (measured best on
+    // the 3x3 lattice), at most RS_CAP lattice rows, and the row buffer within
+    // ~40 KiB of LDS; an explicit count is honoured up to those limits
     const int nfrm = nfr_max(band_h, s, pad);
-    int gs = std::max(1, (4 * c.BS) / std::max(1, s * c.xw));
+    int gs = steps > 0 ? steps : std::max(1, (6 + s / 2) / s);
     gs = std::min({gs, GSUB_CAP, std::max(1, RS_CAP / s)});
-    while (gs > 1 && make_layout(gs * s, c.xw, nfrm).total_bytes > 40 * 1024) --gs;
+    while (gs > 1 && make_layout(gs * s, c.xw, nfrm).total_bytes > (steps > 0 ? 64 : 40) * 1024) --gs;
     c.gsub = gs;
     c.lds = make_layout(gs * s, c.xw, nfrm).total_bytes;
     if (c.lds > 64 * 1024) return fail(GK_EINVAL, "launch shape needs %d bytes of LDS (> 64 KiB)", c.lds);
     return GK_OK;
+}
+
+static void fit_shape(const gk_grid* g, int& bh, int& bw, int bs_fixed) {
+    const std::string saved = g_err;
+    LaunchCfg c;
+    bw = std::max(1, std::min(bw, bs_fixed ? bs_fixed / 4 : 128));
+    while (make_cfg(g, bh, bw, c, bs_fixed) != GK_OK) {
+        if (bw > 8) bw = (bw + 1) / 2;
+        else if (bh > 1) bh = (bh + 1) / 2;
+        else break;
+    }
+    g_err = saved;
 }
 
 template <int MODE>
@@ -911,8 +911,7 @@ struct MultiPlan {
     std::vector<int> shapes;        // band_h, band_w per grid at build time
     FwdArgs* d_args = nullptr;
     int4* d_items = nullptr;
-    unsigned* d_work = nullptr;     // [0] next item, [1] workgroups done
-    int n_items = 0, n_wg = 0, lds = 0;
+    int n_items = 0, lds = 0;
 };
 
 static std::mutex g_plan_mu;
@@ -922,7 +921,6 @@ constexpr size_t MAX_PLANS = 8;
 static void free_plan(MultiPlan* p) {
     if (p->d_args) (void)hipFree(p->d_args);
     if (p->d_items) (void)hipFree(p->d_items);
-    if (p->d_work) (void)hipFree(p->d_work);
     delete p;
 }
 
@@ -940,18 +938,18 @@ static void evict_plans(const gk_grid* g) {
     }
 }
 
-static void multi_band_shape(const gk_grid* g, int rows, int& bh, int& bw) {
-    choose_rule(g, rows, bh, bw);
-    bw = std::min(bw, MULTI_BS / 4);
+static void multi_band_shape(const gk_grid* g, int rows, int& bh, int& bw, int& steps) {
+    choose_rule(g, rows, bh, bw, steps);
+    fit_shape(g, bh, bw, MULTI_BS);
 }
 
 static bool plan_matches(const MultiPlan* p, int device, const gk_grid* const* grids, int n, const int* offs) {
     if (p->device != device || (int)p->grids.size() != n) return false;
     for (int i = 0; i < n; ++i) {
         if (p->grids[i] != grids[i] || p->offs[i] != offs[i]) return false;
-        int bh, bw;
-        multi_band_shape(grids[i], offs[i + 1] - offs[i], bh, bw);
-        if (p->shapes[2 * i] != bh || p->shapes[2 * i + 1] != bw) return false;
+        int bh, bw, st;
+        multi_band_shape(grids[i], offs[i + 1] - offs[i], bh, bw, st);
+        if (p->shapes[3 * i] != bh || p->shapes[3 * i + 1] != bw || p->shapes[3 * i + 2] != st) return false;
     }
     return p->offs[n] == offs[n];
 }
@@ -979,12 +977,13 @@ static int build_plan(int device, const gk_grid* const* grids, int n, const int*
     for (int i = 0; i < n; ++i) {
         const gk_grid* g = grids[i];
         const int rows = offs[i + 1] - offs[i];
-        int bh, bw;
-        multi_band_shape(g, rows, bh, bw);
+        int bh, bw, st;
+        multi_band_shape(g, rows, bh, bw, st);
         p->shapes.push_back(bh);
         p->shapes.push_back(bw);
+        p->shapes.push_back(st);
         LaunchCfg c;
-        int rc = make_cfg(g, bh, bw, c, MULTI_BS);
+        int rc = make_cfg(g, bh, bw, c, MULTI_BS, st);
         if (rc) { free_plan(p); return rc; }
         lds = std::max(lds, c.lds);
         fill_args(g, c, args[i], nullptr, 0);
@@ -998,22 +997,14 @@ static int build_plan(int device, const gk_grid* const* grids, int n, const int*
     for (size_t k = 0; k < items.size(); ++k) it[k] = items[k].it;
     p->n_items = (int)it.size();
     p->lds = lds;
-    int per_cu = 0, n_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel, MULTI_BS, lds) != hipSuccess ||
-        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
-        free_plan(p);
-        return fail(GK_EHIP, "occupancy query for the many-grid kernel failed");
-    }
-    p->n_wg = std::max(1, std::min(p->n_items, std::max(1, per_cu) * n_cu));
     if (hipMalloc((void**)&p->d_args, sizeof(FwdArgs) * n) != hipSuccess ||
-        hipMalloc((void**)&p->d_items, sizeof(int4) * std::max<size_t>(1, it.size())) != hipSuccess ||
-        hipMalloc((void**)&p->d_work, 2 * sizeof(unsigned)) != hipSuccess) {
+        hipMalloc((void**)&p->d_items, sizeof(int4) * std::max<size_t>(1, it.size())) != hipSuccess) {
         free_plan(p);
         return fail(GK_ENOMEM, "allocation of a many-grid plan failed");
     }
     if (hipMemcpy(p->d_args, args.data(), sizeof(FwdArgs) * n, hipMemcpyHostToDevice) != hipSuccess ||
         (!it.empty() && hipMemcpy(p->d_items, it.data(), sizeof(int4) * it.size(), hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemset(p->d_work, 0, 2 * sizeof(unsigned)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipDeviceSynchronize() != hipSuccess) {
         free_plan(p);
         return fail(GK_EHIP, "upload of a many-grid plan failed");
     }
@@ -1160,15 +1151,21 @@ int destroy_grid(gk_grid_t g) {
     return GK_OK;
 }
 
-int set_launch_shape(gk_grid_t g, int batch_min, int band_h, int band_w) {
+int set_launch_shape(gk_grid_t g, int batch_min, int band_h, int band_w, int steps) {
     if (!g) return fail(GK_EINVAL, "grid is NULL");
     if (batch_min < 1 || band_h < 1 || band_w < 1) return fail(GK_EINVAL, "batch_min, band_h, band_w must be >= 1");
+    if (steps < 0 || steps > GSUB_CAP) return fail(GK_EINVAL, "steps must be in [0, %d]", GSUB_CAP);
     LaunchCfg c;
-    int rc = make_cfg(g, std::min(band_h, g->d.ny), std::min(band_w, g->d.nx), c);
+    int rc = make_cfg(g, std::min(band_h, g->d.ny), std::min(band_w, g->d.nx), c, 0, steps);
     if (rc) return rc;
     for (auto& r : g->rules)
-        if (r.batch_min == batch_min) { r.band_h = band_h; r.band_w = band_w; return GK_OK; }
-    g->rules.push_back({batch_min, band_h, band_w});
+        if (r.batch_min == batch_min) {
+            r.band_h = band_h;
+            r.band_w = band_w;
+            r.steps = steps;
+            return GK_OK;
+        }
+    g->rules.push_back({batch_min, band_h, band_w, steps});
     return GK_OK;
 }
 
@@ -1222,10 +1219,10 @@ int loglike_batch(gk_grid_t g, const double* theta, int B, int stride, double* l
     if (rc) return rc;
     if (!g->has_data) return fail(GK_ESTATE, "loglike_batch before set_data");
     if (B == 0) return GK_OK;
-    int bh, bw;
-    choose_rule(g, B, bh, bw);
+    int bh, bw, steps;
+    choose_rule(g, B, bh, bw, steps);
     LaunchCfg c;
-    rc = make_cfg(g, bh, bw, c);
+    rc = make_cfg(g, bh, bw, c, 0, steps);
     if (rc) return rc;
     FwdArgs a;
     fill_args(g, c, a, theta, stride);
@@ -1239,10 +1236,10 @@ int eval_maps(gk_grid_t g, const double* theta, int B, int stride, float* maps, 
     int rc = check_call(g, theta, B, stride, maps);
     if (rc) return rc;
     if (B == 0) return GK_OK;
-    int bh, bw;
-    choose_rule(g, B, bh, bw);
+    int bh, bw, steps;
+    choose_rule(g, B, bh, bw, steps);
     LaunchCfg c;
-    rc = make_cfg(g, bh, bw, c);
+    rc = make_cfg(g, bh, bw, c, 0, steps);
     if (rc) return rc;
     FwdArgs a;
     fill_args(g, c, a, theta, stride);
@@ -1261,10 +1258,10 @@ int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, doub
     if (B == 0) return GK_OK;
     hipStream_t st = (hipStream_t)stream;
     // pass 1: log-likelihood and d logL / d F at every pixel
-    int bh, bw;
-    choose_rule(g, B, bh, bw);
+    int bh, bw, steps;
+    choose_rule(g, B, bh, bw, steps);
     LaunchCfg c;
-    rc = make_cfg(g, bh, bw, c);
+    rc = make_cfg(g, bh, bw, c, 0, steps);
     if (rc) return rc;
     FwdArgs fa;
     fill_args(g, c, fa, theta, stride);
@@ -1391,8 +1388,9 @@ int loglike_multi(const gk_grid_t* grids, int n_gal, const double* theta, const 
             g_plans.push_back(p);
         }
     }
-    hipLaunchKernelGGL(multi_kernel, dim3((unsigned)p->n_wg), dim3(MULTI_BS), p->lds, st, p->d_args, p->d_items,
-                       p->n_items, theta, stride, logL, p->d_work);
+    if (p->n_items == 0) return GK_OK;
+    hipLaunchKernelGGL(multi_kernel, dim3((unsigned)p->n_items), dim3(MULTI_BS), p->lds, st, p->d_args, p->d_items,
+                       theta, stride, logL);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(GK_EHIP, "many-grid launch failed: %s", hipGetErrorString(e));
     return GK_OK;
