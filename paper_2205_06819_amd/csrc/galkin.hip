@@ -69,12 +69,12 @@ constexpr int RS_CAP = 16;      // lattice rows per model phase
 constexpr int GSUB_CAP = 4;     // pixel-row steps per model phase
 
 struct Layout {                 // LDS carve-up, identical on host and device
-    int tab, rows, red, rows_lo, rows_start, total_bytes;
+    int tab, rows, red, rows_lo, rows_start, stage, total_bytes;
 };
 
 __host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
 
-__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm) {
+__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int band_h) {
     Layout L;
     int off = 0;                                   // in 4-byte words
     L.tab = off;        off += TAB_ALL;
@@ -83,6 +83,8 @@ __host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm) {
     L.red = off;        off += 2 * RED_SLOTS;      // doubles
     L.rows_lo = off;    off += nfrm;
     L.rows_start = off; off += nfrm + 1 + RS_CAP;  // padded: phase lookups read ahead
+    off = (off + 1) & ~1;
+    L.stage = off;      off += 2 * band_h + 32;    // row spans and stencil half-widths
     L.total_bytes = 4 * off;
     return L;
 }
@@ -180,7 +182,7 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     const int ubase = c0 * s + hs;                  // lattice column of local column 0
     const int nfrm = nfr_max(a.band_h, s, pad);
     const int RS = a.gsub * s;
-    const Layout L = make_layout(RS, a.xw, nfrm);
+    const Layout L = make_layout(RS, a.xw, nfrm, a.band_h);
     float* s_tab = smem + L.tab;
     float* s_rows = smem + L.rows;
     double* s_red = (double*)(smem + L.red);
@@ -211,6 +213,12 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
         for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
     }
     for (int i = tid; i < RS * 4 * XW; i += BS) s_rows[i] = 0.0f;
+    // row spans of the band and stencil half-widths, staged for the span pass
+    int2* s_span = (int2*)(smem + L.stage);
+    int* s_aof = (int*)(s_span + a.band_h);
+    for (int i = tid; i < NR; i += BS) s_span[i] = MODE != MODE_MAPS ? a.span[j0 + i] : make_int2(c0, c1 - 1);
+    for (int i = tid; i <= pad; i += BS) s_aof[i] = a.aof[i];
+    __syncthreads();
     for (int r = tid; r < NFR; r += BS) {
         const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;   // ceil((r - 2 pad) / s)
         const int jhi = min(NR - 1, r / s);
@@ -218,14 +226,10 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
         for (int jj = jlo; jj <= jhi; ++jj) {
             int bb = r - jj * s - pad;
             bb = bb < 0 ? -bb : bb;
-            int cl = c0, ch = c1 - 1;
-            if (MODE != MODE_MAPS) {
-                const int2 sp = a.span[j0 + jj];
-                cl = max(cl, sp.x);
-                ch = min(ch, sp.y);
-            }
+            const int2 sp = s_span[jj];
+            const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
             if (cl <= ch) {
-                const int A = a.aof[bb];
+                const int A = s_aof[bb];
                 lo = min(lo, cl * s + hs + pad - A);
                 hi = max(hi, ch * s + hs + pad + A);
             }
@@ -454,7 +458,8 @@ struct AdjArgs {
 
 __host__ __device__ inline int adj_lds_bytes(int band_h, int band_w, int s, int pad) {
     const int nfrm = nfr_max(band_h, s, pad);
-    return 4 * (TAB_ALL + 4 * band_h * band_w + 64 + 2 * nfrm + 1 + RED_SLOTS * 2 * NCONST + 64);
+    return 4 * (TAB_ALL + 4 * band_h * band_w + 64 + 2 * nfrm + 1 + RED_SLOTS * 2 * NCONST + 64 + 2 * band_h +
+                32);
 }
 
 __device__ inline int floor_div(int n, int d) { return n >= 0 ? n / d : -((-n + d - 1) / d); }
@@ -540,6 +545,8 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
     int* s_lo = (int*)(s_gw + 64);
     int* s_start = s_lo + nfrm;                                    // [nfrm + 1]
     double* s_red = (double*)(((uintptr_t)(s_start + nfrm + 1) + 15) & ~(uintptr_t)15);
+    int2* s_span = (int2*)(s_red + RED_SLOTS * NCONST);           // [band_h] row spans
+    int* s_aof = (int*)(s_span + a.band_h);                        // [pad + 1] half-widths
 
     const double* th = a.theta + (size_t)b * a.stride;
     const TC tc = uniform_tc(make_tc(th, G));
@@ -552,12 +559,15 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
     for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
     for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
     for (int i = tid; i < 64; i += BS) s_gw[i] = a.gw[i];
+    for (int i = tid; i < NR; i += BS) s_span[i] = a.span[j0 + i];
+    for (int i = tid; i <= pad; i += BS) s_aof[i] = a.aof[i];
     const size_t boff = (size_t)b * 4 * G.ny * G.nx, mstr = (size_t)G.ny * G.nx;
     for (int p = tid; p < NR * NC; p += BS) {
         const int jj = p / NC, cc = p - jj * NC;
         const size_t pix = boff + (size_t)(j0 + jj) * G.nx + c0 + cc;
         s_fb[p] = make_float4(a.fbar[pix], a.fbar[pix + mstr], a.fbar[pix + 2 * mstr], a.fbar[pix + 3 * mstr]);
     }
+    __syncthreads();
     for (int r = tid; r < NFR; r += BS) {
         const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
         const int jhi = min(NR - 1, r / s);
@@ -565,10 +575,10 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
         for (int jj = jlo; jj <= jhi; ++jj) {
             int bb = r - jj * s - pad;
             bb = bb < 0 ? -bb : bb;
-            const int2 sp = a.span[j0 + jj];
+            const int2 sp = s_span[jj];
             const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
             if (cl <= ch) {
-                const int A = a.aof[bb];
+                const int A = s_aof[bb];
                 lo = min(lo, cl * s + hs + pad - A);
                 hi = max(hi, ch * s + hs + pad + A);
             }
@@ -601,7 +611,7 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
         for (int jj = jlo; jj <= jhi; ++jj) {
             int bb = r - jj * s - pad;
             bb = bb < 0 ? -bb : bb;
-            const int A = a.aof[bb];
+            const int A = s_aof[bb];
             const float gb = s_gw[bb];
             const int ccl = max(0, -floor_div(-(x - pad - A), s));
             const int cch = min(NC - 1, floor_div(x - pad + A, s));
@@ -621,12 +631,21 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
         point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, f.x * invW, f.y * invW, f.z * invW, f.w * invW, ad);
     }
 
-    // ---- FP64 reduction of the constant adjoints: waves, then bands in order
+    // ---- FP64 reduction of the constant adjoints: waves (all constants
+    // stepped together, so the shuffles overlap), then bands in order
     const int lane = tid & 63, wave = tid >> 6, nw = (BS + 63) >> 6;
+    {
+        double v[NCONST];
 #pragma unroll
-    for (int k = 0; k < NCONST; ++k) {
-        const double v = wave_sum((double)ad[k]);
-        if (lane == 0) s_red[wave * NCONST + k] = v;
+        for (int k = 0; k < NCONST; ++k) v[k] = (double)ad[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+            for (int k = 0; k < NCONST; ++k) v[k] += __shfl_down(v[k], o, 64);
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < NCONST; ++k) s_red[wave * NCONST + k] = v[k];
     }
     __syncthreads();
     double* gp = a.gpart + ((size_t)b * a.nbands + band) * NCONST;
@@ -825,9 +844,9 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int 
     const int nfrm = nfr_max(band_h, s, pad);
     int gs = steps > 0 ? steps : std::max(1, (6 + s / 2) / s);
     gs = std::min({gs, GSUB_CAP, std::max(1, RS_CAP / s)});
-    while (gs > 1 && make_layout(gs * s, c.xw, nfrm).total_bytes > (steps > 0 ? 64 : 40) * 1024) --gs;
+    while (gs > 1 && make_layout(gs * s, c.xw, nfrm, band_h).total_bytes > (steps > 0 ? 64 : 40) * 1024) --gs;
     c.gsub = gs;
-    c.lds = make_layout(gs * s, c.xw, nfrm).total_bytes;
+    c.lds = make_layout(gs * s, c.xw, nfrm, band_h).total_bytes;
     if (c.lds > 64 * 1024) return fail(GK_EINVAL, "launch shape needs %d bytes of LDS (> 64 KiB)", c.lds);
     return GK_OK;
 }
