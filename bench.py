@@ -332,7 +332,9 @@ def main():
     ap.add_argument("--plain", type=int, default=256, help="number of single-vector calls timed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="many-galaxy workload: skip the band-policy search")
+    ap.add_argument("--tune", action="store_true",
+                    help="single-grid workloads: autotune the launch shape (default: the library's defaults)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 512 MiB device copy (traffic-counter calibration)")
@@ -370,7 +372,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuned = None
-    if not args.no_tune:
+    if args.tune:
         tuned = autotune.tune(grid, th, reps=2)
         autotune.tune(grid, th[:1], reps=20)
         # batch sizes between 1 and B keep the default shapes
@@ -460,11 +462,13 @@ def main():
     flop_theta = n_need * flops_per_point(spec) + n_valid * flops_per_pixel(spec)
     achieved = flop_theta * B / (ms_step * 1e-3) / 1e12
     traffic = None
+    shape = list(tuned[:3]) if tuned else None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
     if os.path.exists(tpath):
         try:
             t = json.load(open(tpath))
-            if t.get("source_hash") == source_hash():
+            # counters are valid only for this kernel source and launch shape
+            if t.get("source_hash") == source_hash() and t.get("launch_shape") == shape:
                 traffic = t.get("bytes_per_launch")
         except (OSError, ValueError):
             pass
@@ -506,7 +510,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "batch": B,
                    "spaxels": spax, "valid_spaxels": n_valid, "params": P,
                    "supersample": spec.supersample, "psf_sigma_px": round(spec.psf_sigma_px, 5),
-                   "launch_shape": list(tuned[:3]) if tuned else None},
+                   "launch_shape": list(tuned[:3]) if tuned else "library default"},
         "params_x_spaxels_per_s": round(evals * P * spax, 1),
         "plain_evals_per_s": round(plain_evals, 1),
         "plain_host_loop_evals_per_s": round(plain_loop_evals, 1),

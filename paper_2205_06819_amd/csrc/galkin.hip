@@ -801,11 +801,13 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int 
 static void fit_shape(const gk_grid* g, int& bh, int& bw, int bs_fixed);
 
 static int default_rules(gk_grid* g) {
-    // Large batches: whole frames (up to 128 pixels wide) per workgroup.  Small
-    // batches: small square bands so that one theta spreads over many CUs.
+    // Large batches: bands of up to 40 x 40 pixels (measured best on the 3x3
+    // lattice: enough workgroups per CU to overlap one band's model phase with
+    // another's stencil phase).  Small batches: small square bands so that one
+    // theta spreads over many CUs.
     const int nx = g->d.nx, ny = g->d.ny;
     g->rules.clear();
-    int bh = ny, bw = std::min(nx, 128);
+    int bh = std::min(ny, 40), bw = std::min(nx, 40);
     fit_shape(g, bh, bw, 0);
     g->rules.push_back({512, bh, bw, 0});
     int side = std::max(4, (int)std::ceil(std::sqrt((double)nx * ny / 64.0)));
