@@ -234,14 +234,26 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
                 hi = max(hi, ch * s + hs + pad + A);
             }
         }
-        const int w = hi >= lo ? hi - lo + 1 : 0;
-        s_lo[r] = w ? lo - ubase : 0;               // local column of the first needed point
-        s_start[r] = w;
+        s_lo[r] = hi >= lo ? lo - ubase : (1 << 30);  // local needed columns of lattice row r
+        s_start[r] = hi >= lo ? hi - ubase : -(1 << 30);
     }
     __syncthreads();
-    const int total = block_exclusive_scan(s_start, NFR, (int*)s_red);
-    if (tid == 0)
-        for (int k = 0; k <= RS_CAP; ++k) s_start[NFR + k] = total;
+    // one column range per model phase: the union of its lattice rows' ranges
+    // (about 3 % more points than row by row, and no per-point row search)
+    const int RSs = a.gsub * s;
+    const int nph = (NFR + RSs - 1) / RSs;
+    int* s_plo = (int*)(smem + L.stage);                // reuses the staging area
+    int* s_pw = s_plo + nph;
+    __syncthreads();
+    for (int k = tid; k < nph; k += BS) {
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int r = k * RSs; r < min(NFR, (k + 1) * RSs); ++r) {
+            lo = min(lo, s_lo[r]);
+            hi = max(hi, s_start[r]);
+        }
+        s_plo[k] = hi >= lo ? lo : 0;
+        s_pw[k] = hi >= lo ? hi - lo + 1 : 0;
+    }
     __syncthreads();
 
     const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
@@ -261,18 +273,13 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     const int Q = NR + D;                           // pixel-row steps
 
     for (int q0 = 0; q0 < Q; q0 += a.gsub) {
-        // ---- lattice rows [rA, rA + nrow) of this phase and their flat point ranges
+        // ---- lattice rows [rA, rA + nrow) of this phase, columns [plo, plo + pw)
         const int rA = q0 * s;
         const int nrow = max(0, min(RS, NFR - rA));
-        const int qA = uni(s_start[min(rA, NFR)]);
-        int st[RS_CAP + 1];
-        st[0] = 0;
-#pragma unroll
-        for (int k = 1; k <= RS_CAP; ++k)
-            st[k] = (k <= nrow) ? uni(s_start[rA + k]) - qA : (1 << 30);
-        int npts = 0;
-#pragma unroll
-        for (int k = 1; k <= RS_CAP; ++k) npts = (k == nrow) ? st[k] : npts;
+        const int ph = q0 / a.gsub;
+        const int plo = uni(s_plo[ph]), pw = uni(s_pw[ph]);
+        const int npts = nrow * pw;
+        const float inv_pw = 1.0f / (float)max(pw, 1);
         // ---- data of the pixel rows completed in this phase (prefetched)
         float pv[GSUB_CAP], pi[GSUB_CAP];
         if (MODE != MODE_MAPS) {
@@ -289,26 +296,9 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
         }
         // ---- model phase: the phase's lattice points, flat over its rows
         for (int q = tid; q < npts; q += BS) {
-            // row of point q: compare with every row start (entries past the
-            // phase's rows are huge), no data-dependent indexing
-            int lr = 0, rowq = 0;
-            if (nrow <= 8) {
-#pragma unroll
-                for (int k = 1; k < 8; ++k) {
-                    const bool ge = q >= st[k];
-                    lr += ge ? 1 : 0;
-                    rowq = ge ? st[k] : rowq;
-                }
-            } else {
-#pragma unroll
-                for (int k = 1; k < RS_CAP; ++k) {
-                    const bool ge = q >= st[k];
-                    lr += ge ? 1 : 0;
-                    rowq = ge ? st[k] : rowq;
-                }
-            }
+            const int lr = (int)(((float)q + 0.5f) * inv_pw);
             const int r = rA + lr;
-            const int x = s_lo[r] + (q - rowq);                 // local column
+            const int x = plo + (q - lr * pw);                   // local column
             const int u = ubase + x;
             const int v = vlo + r;
             const float du = (float)(u - tc.Ui) - tc.Uf;
