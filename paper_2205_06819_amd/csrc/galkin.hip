@@ -77,7 +77,6 @@ __host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (ban
 __host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int band_h) {
     Layout L;
     int off = 0;                                   // in 4-byte words
-    L.tab = off;        off += TAB_ALL;
     L.rows = off;       off += rows * 4 * xw;
     off = (off + 3) & ~3;
     L.red = off;        off += 2 * RED_SLOTS;      // doubles
@@ -85,6 +84,10 @@ __host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int ba
     L.rows_start = off; off += nfrm + 1 + RS_CAP;  // padded: phase lookups read ahead
     off = (off + 1) & ~1;
     L.stage = off;      off += 2 * band_h + 32;    // row spans and stencil half-widths
+    // the tables last, at a launch-dependent offset: a table lookup is then one
+    // base add and four reads with immediate offsets
+    off = (off + 3) & ~3;
+    L.tab = off;        off += TAB_ALL;
     L.total_bytes = 4 * off;
     return L;
 }
@@ -830,11 +833,12 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int 
         c.BS = bs_fixed;
     }
     c.xw = band_w * s + 2 * pad + 1;
-    // pixel-row steps per model phase: about six lattice rows (measured best on
-    // the 3x3 lattice), at most RS_CAP lattice rows, and the row buffer within
-    // ~40 KiB of LDS; an explicit count is honoured up to those limits
+    // pixel-row steps per model phase: about ten lattice rows (measured best on
+    // the 3x3 lattice with 40x40 bands), at most RS_CAP lattice rows, and the
+    // row buffer within ~40 KiB of LDS; an explicit count is honoured up to
+    // those limits
     const int nfrm = nfr_max(band_h, s, pad);
-    int gs = steps > 0 ? steps : std::max(1, (6 + s / 2) / s);
+    int gs = steps > 0 ? steps : std::max(1, (10 + s / 2) / s);
     gs = std::min({gs, GSUB_CAP, std::max(1, RS_CAP / s)});
     while (gs > 1 && make_layout(gs * s, c.xw, nfrm, band_h).total_bytes > (steps > 0 ? 64 : 40) * 1024) --gs;
     c.gsub = gs;

@@ -154,10 +154,13 @@ __device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x
 
 // Piece index and local coordinate u in [-1, 1) of x in [2^elo, 2^ehi):
 // quarter-octave pieces selected by the exponent and the top two mantissa bits.
+// Callers only pass x >= 2^elo; the bias is removed before the shift so the
+// index is formed without a negative constant (the four table reads then
+// share one address and use immediate offsets).
 __device__ __forceinline__ int piece(float x, int elo, float& u) {
     const uint32_t b = __float_as_uint(x);
     u = __uint_as_float(0x3f800000u | ((b & 0x1FFFFFu) << 2)) * 2.0f - 3.0f;
-    return (int)(b >> 21) - ((127 + elo) << 2);
+    return (int)((b - ((uint32_t)(127 + elo) << 23)) >> 21);
 }
 // du/dx for the piece containing x: the piece has half-width 2^(e-3).
 __device__ __forceinline__ float piece_dudx(float x) {
