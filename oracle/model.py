@@ -251,19 +251,28 @@ def psf_maps(spec: GridSpec, theta) -> np.ndarray:
     return convolve_lattice(spec, model_lattice(spec, theta))
 
 
+def psf_pixels(spec: GridSpec, theta, pixels) -> np.ndarray:
+    """PSF-averaged (B, v, sigma, <L/M>) at the listed pixels [(i, j), ...],
+    [4, n], with the structure of Appendix A, Algorithm 1: each pixel
+    evaluates the model at its K own sub-grid points and averages them.
+    Cost is K model evaluations per pixel, so it serves grids too large for
+    the whole-lattice path."""
+    taps, W, _ = stencil(spec)
+    s = spec.supersample
+    offs = np.array([(a / s, b / s) for a, b, _ in taps])
+    wts = np.array([w for _, _, w in taps])
+    out = np.zeros((4, len(pixels)))
+    for n, (i, j) in enumerate(pixels):
+        vals = point_model(spec, theta, i + offs[:, 0], j + offs[:, 1])
+        out[:, n] = vals @ wts / W
+    return out
+
+
 def psf_maps_alg1(spec: GridSpec, theta) -> np.ndarray:
     """Same as ``psf_maps`` with the structure of Appendix A, Algorithm 1: for
     every pixel, evaluate the model at its K own sub-grid points and average."""
-    taps, W, _ = stencil(spec)
-    s = spec.supersample
-    out = np.zeros((4, spec.ny, spec.nx))
-    offs = np.array([(a / s, b / s) for a, b, _ in taps])
-    wts = np.array([w for _, _, w in taps])
-    for j in range(spec.ny):
-        for i in range(spec.nx):
-            vals = point_model(spec, theta, i + offs[:, 0], j + offs[:, 1])
-            out[:, j, i] = vals @ wts / W
-    return out
+    pix = [(i, j) for j in range(spec.ny) for i in range(spec.nx)]
+    return psf_pixels(spec, theta, pix).reshape(4, spec.ny, spec.nx)
 
 
 # ---------------------------------------------------------------------------
