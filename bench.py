@@ -281,9 +281,13 @@ def bench_uneven(args):
         g.close()
 
 
-def time_hmc(gk, grid, th, n_steps: int, eps: float = 1e-4) -> dict:
+def time_hmc(gk, grid, th, n_steps: int, eps: float = 1e-9) -> dict:
     """One leapfrog trajectory of n_steps for every row, captured once in a
-    HIP graph and replayed from the same start (restored outside the timing)."""
+    HIP graph and replayed once (a one-step eager trajectory first loads the
+    kernels; the start is restored outside the timing).  The rows are prior
+    draws far from the data's truth, where |d logL / d theta| reaches ~1e10:
+    the small step keeps every row inside the valid domain, so no row is
+    frozen and every step does the full work."""
     import torch
     B, P = th.shape
     dev = th.device
@@ -296,25 +300,24 @@ def time_hmc(gk, grid, th, n_steps: int, eps: float = 1e-4) -> dict:
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        gk.hmc_leapfrog(grid.handle, theta, mom, inv_mass, eps, n_steps, logL, grad)
+        gk.hmc_leapfrog(grid.handle, theta, mom, inv_mass, eps, 1, logL, grad)
     torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         gk.hmc_leapfrog(grid.handle, theta, mom, inv_mass, eps, n_steps, logL, grad)
+    theta.copy_(th)
+    mom.copy_(mom0)
+    torch.cuda.synchronize()
+    print(f"hmc: graph of {n_steps} leapfrog steps captured, replaying", file=sys.stderr, flush=True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    times = []
-    for _ in range(2):
-        theta.copy_(th)
-        mom.copy_(mom0)
-        torch.cuda.synchronize()
-        e0.record()
-        graph.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
     frozen = int((~torch.isfinite(logL)).sum())
     del graph
-    ms = min(times)
     return {"hmc_steps": n_steps, "ms_per_hmc_trajectory": ms,
             "hmc_grad_evals_per_s": B * (n_steps + 1) / (ms * 1e-3), "hmc_rows_frozen": frozen}
 
