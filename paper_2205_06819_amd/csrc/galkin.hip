@@ -439,6 +439,7 @@ struct AdjArgs {
     const float* gw;        // [64] 1-D Gaussian factors
     const int* aof;         // [pad + 1] stencil half-widths
     float invW;
+    int D;                  // pixel-row lags of the stencil, floor(2 pad / s)
     const int2* span;       // [ny] valid column spans
     int band_h, band_w, nbx, nbands;
     const double* theta;
@@ -591,6 +592,8 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
 #pragma unroll
     for (int k = 0; k < NCONST; ++k) ad[k] = 0.0f;
     const float invW = a.invW;
+    const float inv_s = 1.0f / (float)s;
+    const int D = a.D;
     int rcur = 0;
     for (int q = tid; q < total; q += BS) {
         while (s_start[rcur + 1] <= q) ++rcur;
@@ -599,15 +602,21 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
         // transposed stencil: this lattice point's share of every band pixel
         // whose 3 sigma disc contains it, weighted by that pixel's adjoint
         float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
-        const int jhi = min(NR - 1, r / s);
+        // pixel rows jj = jq - d and columns cc = cq - k around the point; the
+        // divisions by s go through a float reciprocal (exact for these sizes)
+        const int jq = (int)(((float)r + 0.5f) * inv_s), rr = r - jq * s - pad;
+        const int cq = (int)(((float)x + 0.5f) * inv_s), rx = x - cq * s - pad;
+        const int jlo = max(0, jq - D), jhi = min(NR - 1, jq);
         for (int jj = jlo; jj <= jhi; ++jj) {
-            int bb = r - jj * s - pad;
+            int bb = rr + (jq - jj) * s;
             bb = bb < 0 ? -bb : bb;
+            if (bb > pad) continue;
             const int A = s_aof[bb];
             const float gb = s_gw[bb];
-            const int ccl = max(0, -floor_div(-(x - pad - A), s));
-            const int cch = min(NC - 1, floor_div(x - pad + A, s));
+            // columns with |x - cc s - pad| <= A: k = cq - cc in [(pad - A - rx') / s, (pad + A - rx') / s]
+            const int klo = max(0, (int)floorf((float)(-A - rx + s - 1) * inv_s + 1e-4f));
+            const int khi = min(D, (int)floorf((float)(A - rx) * inv_s + 1e-4f));
+            const int ccl = max(0, cq - khi), cch = min(NC - 1, cq - klo);
             for (int cc = ccl; cc <= cch; ++cc) {
                 int aa = x - cc * s - pad;
                 aa = aa < 0 ? -aa : aa;
@@ -800,7 +809,9 @@ static int default_rules(gk_grid* g) {
     // theta spreads over many CUs.
     const int nx = g->d.nx, ny = g->d.ny;
     g->rules.clear();
-    int bh = std::min(ny, 40), bw = std::min(nx, 40);
+    // the grid split into near-equal bands of at most 40 pixels each way
+    int bh = (ny + (ny + 39) / 40 - 1) / ((ny + 39) / 40);
+    int bw = (nx + (nx + 39) / 40 - 1) / ((nx + 39) / 40);
     fit_shape(g, bh, bw, 0);
     g->rules.push_back({512, bh, bw, 0});
     int side = std::max(4, (int)std::ceil(std::sqrt((double)nx * ny / 64.0)));
@@ -1290,6 +1301,7 @@ int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, doub
     aa.gw = g->d_gw;
     aa.aof = g->d_aof;
     aa.invW = g->invW;
+    aa.D = g->D;
     aa.span = g->d_span;
     aa.band_h = g->adj_band_h;
     aa.band_w = g->adj_band_w;
