@@ -53,7 +53,7 @@ from typing import Dict, Tuple
 
 import numpy as np
 
-from workloads import (BULGE_NONE, HALO_HERNQUIST, HALO_NFW, HALO_NONE, GridSpec,
+from workloads import (BULGE_JAFFE, BULGE_NONE, HALO_HERNQUIST, HALO_NFW, HALO_NONE, GridSpec,
                        param_names)
 from . import special
 
@@ -144,13 +144,20 @@ def point_model(spec: GridSpec, theta, x_px, y_px):
         MLb = p["MLb"]
         s = R / Rb
         s = np.where(np.real(s) < S_CLAMP, S_CLAMP + 0.0 * s, s)
-        Sig_b = 1.0e-6 * Mb * special.hq_g(s) / (2.0 * math.pi * Rb * Rb)
+        if spec.bulge == BULGE_JAFFE:
+            # Appendix B: Sigma_b = Mb g / Rb^2, Sigma_b sigma_b^2 = G Mb^2 h / (4 pi Rb^3),
+            # v_c^2 = G Mb / (r + Rb)
+            Sig_b = 1.0e-6 * Mb * special.jf_g(s) / (Rb * Rb)
+            BS2 = BS2 + 1.0e-6 * G_KPC * Mb * Mb * special.jf_h(s) / (4.0 * math.pi * Rb ** 3 * MLb)
+            vint2 = vint2 + G_KPC * Mb / (r + Rb)
+        else:
+            Sig_b = 1.0e-6 * Mb * special.hq_g(s) / (2.0 * math.pi * Rb * Rb)
+            # B_b sigma_b^2 = (Sigma_b / ML) G Mb^2 h / (12 pi Rb^3 Sigma_b)
+            BS2 = BS2 + 1.0e-6 * G_KPC * Mb * Mb * special.hq_h(s) / (12.0 * math.pi * Rb ** 3 * MLb)
+            vint2 = vint2 + G_KPC * Mb * r / (r + Rb) ** 2
         B_b = Sig_b / MLb
-        # B_b sigma_b^2 = (Sigma_b / ML) G Mb^2 h / (12 pi Rb^3 Sigma_b)
-        BS2 = BS2 + 1.0e-6 * G_KPC * Mb * Mb * special.hq_h(s) / (12.0 * math.pi * Rb ** 3 * MLb)
         B_tot = B_tot + B_b
         Sig_tot = Sig_tot + Sig_b
-        vint2 = vint2 + G_KPC * Mb * r / (r + Rb) ** 2
 
     # 3. discs (densities now; kinematics need the total v_int first)
     discs = []

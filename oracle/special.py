@@ -28,6 +28,19 @@ as a separate basis element) from the printed formula itself; the vanishing
 of the low-order coefficients that must cancel is asserted when the module is
 imported, which checks the transcription of the formula.
 
+Jaffe bulge, Appendix B (projected density and projected dispersion
+equations; same X(s)):
+
+* ``jf_g(s)`` = 1/(4s) + [1 - (2 - s^2) X(s)] / (2 pi (1 - s^2)), so that the
+  projected density is M_b g / R_b^2;
+* ``jf_h(s)`` = [pi/(2s) + 11 - (13/2) pi s - 12 s^2 + 6 pi s^3
+  - X(s)(6 - 19 s^2 + 12 s^4)] / (1 - s^2), so that
+  Sigma_b sigma_b^2 = G M_b^2 h / (4 pi R_b^3).
+
+Both cancel at s = 1 (removable) and at large s (g ~ s^-3, h ~ s^-4 while
+the printed terms grow); the same exact-series treatment applies, with the
+series kept in a (rational, pi) or (rational, 1/pi) basis.
+
 Exponential (Freeman) disc, paper Sec. 2.3, circular-velocity equation: the
 printed form is dimensionally garbled; the oracle uses the form of the cited
 Binney & Tremaine text, v^2 = (2 G M_d / R_d) y^2 [I0 K0 - I1 K1](y) with
@@ -161,6 +174,78 @@ H_W = np.array([float(c) for c in _H_W])
 assert all(abs(c) < 1e-12 for c in H_W[:4]), H_W[:5]
 assert abs(H_W[4] - 1.6) < 1e-12, H_W[4]
 
+# ---------------------------------------------------------------------------
+# Jaffe series
+# ---------------------------------------------------------------------------
+def _binom_half(n: int, a: Fraction) -> List[Fraction]:
+    """(1 - t)^a = sum_k binom(a, k) (-t)^k, a rational."""
+    out = [Fraction(0)] * n
+    c = Fraction(1)
+    for k in range(n):
+        out[k] = c if k % 2 == 0 else -c
+        c = c * (a - k) / (k + 1)
+    return out
+
+
+def _jaffe_series_t():
+    """Series in t = 1 - s^2: g = 1/(4s) + Gq(t) / (2 pi); h = Hq(t) + pi Hp(t)."""
+    n = NTERMS + 2
+    X = [Fraction(1, 2 * k + 1) for k in range(n)]
+    s2 = _poly({0: 1, 1: -1}, n)
+    s4 = _mul(s2, s2, n)
+    # g: [1 - (2 - s^2) X] / t
+    num = _add(_poly({0: 1}, n), _scale(_mul(_add(_poly({0: 2}, n), _scale(s2, -1), n=n), X, n), -1), n=n)
+    assert num[0] == 0, "Jaffe g numerator must vanish at s = 1"
+    Gq = num[1:NTERMS + 1]
+    # h bracket, pi part: (1/2) s^-1 - (13/2) s + 6 s^3 ; rational part: 11 - 12 s^2 - X (6 - 19 s^2 + 12 s^4)
+    s_m1 = _binom_half(n, Fraction(-1, 2))
+    s_p1 = _binom_half(n, Fraction(1, 2))
+    s_p3 = _binom_half(n, Fraction(3, 2))
+    Bp = _add(_scale(s_m1, Fraction(1, 2)), _scale(s_p1, Fraction(-13, 2)), _scale(s_p3, 6), n=n)
+    Bq = _add(_poly({0: 11}, n), _scale(s2, -12),
+              _scale(_mul(X, _add(_poly({0: 6}, n), _scale(s2, -19), _scale(s4, 12), n=n), n), -1), n=n)
+    assert Bp[0] == 0 and Bq[0] == 0, "Jaffe h bracket must vanish at s = 1"
+    return Gq, Bq[1:NTERMS + 1], Bp[1:NTERMS + 1]
+
+
+def _jaffe_series_w():
+    """Series in w = 1/s (s > 1): g = Gr(w) + Gi(w) / pi, h = Hq(w) + pi Hp(w)."""
+    from math import comb
+    n = NTERMS_W + 4
+    inv_sqrt = [Fraction(0)] * n
+    asin = [Fraction(0)] * n
+    for k in range(n // 2 + 1):
+        if 2 * k < n:
+            inv_sqrt[2 * k] = Fraction(comb(2 * k, k), 4 ** k)
+        if 2 * k + 1 < n:
+            asin[2 * k + 1] = Fraction(comb(2 * k, k), 4 ** k * (2 * k + 1))
+    Y_pi = _scale(inv_sqrt, Fraction(1, 2))             # X = w (Y_q + pi Y_pi)
+    Y_q = _scale(_mul(asin, inv_sqrt, n), -1)
+    geo = [Fraction(1) if k % 2 == 0 else Fraction(0) for k in range(n)]   # 1 / (1 - w^2)
+    # g = w/4 - (w - 2 w^3) Y_pi / (2 (1 - w^2)) - [w^2 + (w - 2 w^3) Y_q] / (2 pi (1 - w^2))
+    a = _poly({1: 1, 3: -2}, n)
+    Gr = _add(_poly({1: Fraction(1, 4)}, n), _scale(_mul(_mul(a, Y_pi, n), geo, n), Fraction(-1, 2)), n=n)
+    Gi = _scale(_mul(_add(_poly({2: 1}, n), _mul(a, Y_q, n), n=n), geo, n), Fraction(-1, 2))
+    assert Gr[0] == Gr[1] == Gr[2] == 0 and Gi[0] == Gi[1] == Gi[2] == 0, "Jaffe g must fall as s^-3"
+    # h = -B3 / (w (1 - w^2)), B3 = w^3 x bracket
+    P = _poly({0: 12, 2: -19, 4: 6}, n)
+    B3p = _add(_poly({4: Fraction(1, 2), 2: Fraction(-13, 2), 0: 6}, n), _scale(_mul(Y_pi, P, n), -1), n=n)
+    B3q = _add(_poly({3: 11, 1: -12}, n), _scale(_mul(Y_q, P, n), -1), n=n)
+    assert B3p[0] == 0 and B3q[0] == 0, "Jaffe h: leading terms must cancel"
+    Hp = _scale(_mul(B3p[1:] + [Fraction(0)], geo, n), -1)
+    Hq = _scale(_mul(B3q[1:] + [Fraction(0)], geo, n), -1)
+    for k in range(4):
+        assert Hp[k] == 0 and Hq[k] == 0, ("Jaffe h must fall as s^-4", k)
+    return Gr[:NTERMS_W], Gi[:NTERMS_W], Hq[:NTERMS_W], Hp[:NTERMS_W]
+
+
+_JG_T, _JHq_T, _JHp_T = _jaffe_series_t()
+_JGr_W, _JGi_W, _JHq_W, _JHp_W = _jaffe_series_w()
+JG_T = np.array([float(c) for c in _JG_T])
+JH_T = np.array([float(q + p * PI_FRACTION) for q, p in zip(_JHq_T, _JHp_T)])
+JG_W = np.array([float(r + i / PI_FRACTION) for r, i in zip(_JGr_W, _JGi_W)])
+JH_W = np.array([float(q + p * PI_FRACTION) for q, p in zip(_JHq_W, _JHp_W)])
+
 # domain split (on the real part of s)
 T_SERIES_MAX = 0.6          # |1 - s^2| <= 0.6, i.e. 0.632 <= s <= 1.265
 W_SERIES_MIN_S = 1.2649     # h at s >= 1.2649 from the w series (w <= 0.7906)
@@ -227,6 +312,39 @@ def hq_h(s):
     num = (-3.0 * s2 * hq_X(sd) * (8.0 * s6 - 28.0 * s4 + 35.0 * s2 - 20.0)
            - 24.0 * s6 + 68.0 * s4 - 65.0 * s2 + 6.0)
     out[direct] = num / (2.0 * td ** 3) - 6.0 * np.pi * sd
+    return out
+
+
+def jf_g(s):
+    """Jaffe projected density: Sigma_b = M_b g / R_b^2 (Appendix B); s > 0."""
+    s = _as_array(s)
+    out = np.empty_like(s)
+    t = 1.0 - s * s
+    near = np.abs(t.real) <= T_SERIES_MAX
+    big = (~near) & (s.real >= W_SERIES_MIN_S)
+    direct = ~(near | big)
+    out[near] = 0.25 / s[near] + _horner(JG_T, t[near]) / (2.0 * np.pi)
+    out[big] = _horner(JG_W, 1.0 / s[big])
+    sd, td = s[direct], t[direct]
+    out[direct] = 0.25 / sd + (1.0 - (2.0 - sd * sd) * hq_X(sd)) / (2.0 * np.pi * td)
+    return out
+
+
+def jf_h(s):
+    """Jaffe projected dispersion: Sigma_b sigma_b^2 = G M_b^2 h / (4 pi R_b^3) (Appendix B)."""
+    s = _as_array(s)
+    out = np.empty_like(s)
+    t = 1.0 - s * s
+    near = np.abs(t.real) <= T_SERIES_MAX
+    big = (~near) & (s.real >= W_SERIES_MIN_S)
+    direct = ~(near | big)
+    out[near] = _horner(JH_T, t[near])
+    out[big] = _horner(JH_W, 1.0 / s[big])
+    sd, td = s[direct], t[direct]
+    s2 = sd * sd
+    br = (np.pi / (2.0 * sd) + 11.0 - 6.5 * np.pi * sd - 12.0 * s2 + 6.0 * np.pi * s2 * sd
+          - hq_X(sd) * (6.0 - 19.0 * s2 + 12.0 * s2 * s2))
+    out[direct] = br / td
     return out
 
 

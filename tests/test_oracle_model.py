@@ -241,3 +241,55 @@ def test_paper_table_masses_bookkeeping():
     for tag, lb, ld1, ld2, total in rows:
         s = sum(10 ** float(v) for v in (lb, ld1, ld2))
         assert s == pytest.approx(float(total), rel=0.02), tag
+
+
+def test_jaffe_bulge_only_dispersion_ml_and_sky_mass():
+    spec = spec_small(bulge=W.BULGE_JAFFE, n_discs=0, halo=W.HALO_NONE)
+    th = theta_for(spec)
+    x, y = sky_from_disc_frame(spec, th, XP, YP)
+    out = M.point_model(spec, th, x, y)
+    p = M.unpack(spec, th)
+    Mb, Rb = 10 ** p["logMb"], p["Rb"]
+    s = np.sqrt(XP ** 2 + YP ** 2) / Rb
+    # Appendix B: sigma^2 = G Mb^2 h / (4 pi Rb^3 Sigma), Sigma = Mb g / Rb^2
+    np.testing.assert_allclose(out[2] ** 2, M.G_KPC * Mb / Rb * S.jf_h(s) / (4 * math.pi * S.jf_g(s)),
+                               rtol=1e-12)
+    np.testing.assert_allclose(out[3], 1.0 / p["MLb"], rtol=1e-14)
+    assert np.max(np.abs(out[1])) == 0.0
+    # the sky-integrated bulge mass on a grid of 5 R_b half-width (centre on a
+    # pixel corner) against the 2-D quadrature of the projected density over
+    # the same square (a units, one quadrant times four)
+    big = W.GridSpec(200, 200, 0.01, 1, 0.1, W.BULGE_JAFFE, 0, W.HALO_NONE)
+    thb = np.array([0.0, 0.0, 0.0, 45.0, 10.0, 0.2, 1.0])
+    jj, ii = np.mgrid[0:big.ny, 0:big.nx]
+    ob = M.point_model(big, thb, ii.astype(float), jj.astype(float))
+    # the cusp (Sigma ~ 1/R) defeats the midpoint rule in the central cells, so
+    # the central 20 x 20 pixels are left out of both sides
+    keep = (np.abs(ii - 99.5) > 10) | (np.abs(jj - 99.5) > 10)
+    sky = (ob[0] / ob[3] * 1e6)[keep].sum() * big.pixel_kpc ** 2 / 1e10
+    from scipy import integrate
+    half, core = 100 * big.pixel_kpc / 0.2, 10 * big.pixel_kpc / 0.2
+    f = lambda v, u: S.jf_g(np.array([math.hypot(u, v)]))[0]
+    q_all, _ = integrate.dblquad(f, 0, half, 0, half, epsrel=1e-9)
+    q_core, _ = integrate.dblquad(f, 0, core, 0, core, epsrel=1e-9)
+    assert sky == pytest.approx(4 * (q_all - q_core), rel=1e-3)   # midpoint rule, h = R_b / 20
+
+
+def test_jaffe_bulge_circular_velocity_enters_vint():
+    spec = spec_small(bulge=W.BULGE_JAFFE, n_discs=1, halo=W.HALO_NONE)
+    th = theta_for(spec, k1=0.0)
+    x, y = sky_from_disc_frame(spec, th, XP, YP)
+    out = M.point_model(spec, th, x, y)
+    p = M.unpack(spec, th)
+    incl = math.radians(p["incl"])
+    r = np.sqrt(XP ** 2 + (YP / math.cos(incl)) ** 2)
+    vb2 = M.G_KPC * 10 ** p["logMb"] / (r + p["Rb"])
+    vd2 = 2 * M.G_KPC * 10 ** p["logMd1"] / p["Rd1"] * S.freeman_phi(r / (2 * p["Rd1"]))
+    # k = 0: the disc's sigma^2 = (vb2 + vd2) / 3, light-weighted with the bulge's
+    Md, Rd, MLd = 10 ** p["logMd1"], p["Rd1"], p["MLd1"]
+    Bd = 1e-6 * Md * np.exp(-r / Rd) / (2 * math.pi * Rd ** 2 * math.cos(incl)) / MLd
+    Mb, Rb = 10 ** p["logMb"], p["Rb"]
+    s = np.sqrt(XP ** 2 + YP ** 2) / Rb
+    Bb = 1e-6 * Mb * S.jf_g(s) / Rb ** 2 / p["MLb"]
+    BbS2 = 1e-6 * M.G_KPC * Mb ** 2 * S.jf_h(s) / (4 * math.pi * Rb ** 3 * p["MLb"])
+    np.testing.assert_allclose(out[2] ** 2, (BbS2 + Bd * (vb2 + vd2) / 3) / (Bb + Bd), rtol=1e-11)

@@ -193,3 +193,83 @@ def test_gravitational_constant_in_kpc_units():
     # 0.5 arcsec at 50 Mpc
     import workloads as W
     assert W.PK_50MPC == pytest.approx(50e3 * 0.5 / 206264.806247, rel=1e-9)
+
+
+# --- Jaffe (Appendix B; G = M = a = 1 units) ---------------------------------
+def rho_jf(r):
+    """Jaffe density (Appendix B, first equation)."""
+    return 1.0 / (4.0 * math.pi * r * r * (r + 1.0) ** 2)
+
+
+def mass_jf(r):
+    return r / (r + 1.0)
+
+
+def sigma_r2_jf_jeans(r):
+    """Isotropic Jeans equation by quadrature for the Jaffe sphere."""
+    val, _ = integrate.quad(lambda u: rho_jf(r * math.exp(u)) * mass_jf(r * math.exp(u))
+                            / (r * math.exp(u)), 0.0, 60.0, epsabs=0, epsrel=1e-13, limit=400)
+    return val / rho_jf(r)
+
+
+@pytest.mark.parametrize("s", S_GRID)
+def test_jaffe_surface_density_is_abel_projection_of_rho(s):
+    # Sigma_b = M g(s) / a^2
+    assert S.jf_g(np.array([s]))[0] == pytest.approx(abel(rho_jf, s), rel=1e-9)
+
+
+@pytest.mark.parametrize("s", [0.05, 0.3, 0.7, 0.99, 1.01, 1.3, 3.0, 8.0])
+def test_jaffe_projected_dispersion_matches_jeans_projection(s):
+    # Sigma sigma_p^2 = G M^2 h / (4 pi a^3), from brute-force Jeans quadrature
+    jeans = abel(lambda r: rho_jf(r) * sigma_r2_jf_jeans(r), s)
+    assert S.jf_h(np.array([s]))[0] / (4.0 * math.pi) == pytest.approx(jeans, rel=2e-7)
+
+
+def test_jaffe_circular_velocity_is_enclosed_mass():
+    # v_c^2 = G M(r) / r with M(r) from the density by quadrature equals G M / (r + a)
+    for r in (0.01, 0.5, 2.0, 40.0):
+        m, _ = integrate.quad(lambda x: 4.0 * math.pi * x * x * rho_jf(x), 0.0, r, epsrel=1e-12, limit=200)
+        assert m / r == pytest.approx(1.0 / (r + 1.0), rel=1e-9)
+
+
+def test_jaffe_total_projected_mass_is_one():
+    f = lambda x: 2.0 * math.pi * x * S.jf_g(np.array([x]))[0]
+    v1, _ = integrate.quad(f, 0, 1, limit=200)
+    v2, _ = integrate.quad(f, 1, np.inf, limit=400)
+    assert v1 + v2 == pytest.approx(1.0, rel=1e-8)
+
+
+def test_jaffe_limits_and_series_continuity():
+    # small s: Sigma -> 1/(4s) (the 1/r^2 cusp) and h -> pi/(2s); large s: both fall
+    # as the r^-4 density tail: s^3 g -> 1/4 ... checked against the Abel tail
+    s = 1e-6
+    assert S.jf_g(np.array([s]))[0] * s == pytest.approx(0.25, rel=1e-4)
+    assert S.jf_h(np.array([s]))[0] * s == pytest.approx(math.pi / 2, rel=1e-4)
+    big = 200.0
+    assert S.jf_g(np.array([big]))[0] == pytest.approx(abel(rho_jf, big), rel=1e-8)
+    for edge in [math.sqrt(1 - S.T_SERIES_MAX), math.sqrt(1 + S.T_SERIES_MAX), S.W_SERIES_MIN_S]:
+        lo, hi = edge * (1 - 1e-12), edge * (1 + 1e-12)
+        for f in (S.jf_g, S.jf_h):
+            a, b = f(np.array([lo, hi]))
+            assert a == pytest.approx(b, rel=1e-11)
+
+
+def test_jaffe_mpmath_agreement_dense():
+    mp.mp.dps = 60
+
+    def X(s):
+        return mp.acosh(1 / s) / mp.sqrt(1 - s * s) if s < 1 else mp.asec(s) / mp.sqrt(s * s - 1)
+
+    def g(s):
+        return 1 / (4 * s) + (1 - (2 - s * s) * X(s)) / (2 * mp.pi * (1 - s * s))
+
+    def h(s):
+        return (mp.pi / (2 * s) + 11 - mp.mpf(13) / 2 * mp.pi * s - 12 * s ** 2 + 6 * mp.pi * s ** 3
+                - X(s) * (6 - 19 * s ** 2 + 12 * s ** 4)) / (1 - s * s)
+
+    ss = np.concatenate([np.geomspace(1e-5, 0.99, 40), np.geomspace(1.01, 1e4, 40)])
+    with mp.workdps(200):
+        ref_g = np.array([float(g(mp.mpf(float(x)))) for x in ss])
+        ref_h = np.array([float(h(mp.mpf(float(x)))) for x in ss])
+    assert np.max(np.abs(S.jf_g(ss) / ref_g - 1)) < 1e-12
+    assert np.max(np.abs(S.jf_h(ss) / ref_h - 1)) < 1e-12

@@ -34,7 +34,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 # Components
-BULGE_NONE, BULGE_HERNQUIST = 0, 1
+BULGE_NONE, BULGE_HERNQUIST, BULGE_JAFFE = 0, 1, 2
 HALO_NONE, HALO_HERNQUIST, HALO_NFW = 0, 1, 2
 
 ARCSEC_PER_RAD = 180.0 * 3600.0 / math.pi
