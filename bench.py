@@ -41,6 +41,8 @@ WORKLOAD_TEXT = {
                "4096 parameter vectors",
     "stress": "300x300 spaxels, 5x5 supersampling, PSF FWHM 4 px, 4 components (17 params), "
               "8192 parameter vectors",
+    "jaffe": "realistic IFU cube with a Jaffe bulge (Appendix B): 80x80 spaxels, 3x3 supersampling, "
+             "PSF FWHM 2.5 px, Jaffe bulge + 2 discs + NFW halo (17 params), 1024 parameter vectors",
 }
 
 
@@ -51,7 +53,7 @@ WORKLOAD_TEXT = {
 def flops_per_point(spec) -> int:
     f = 13                                   # frame: rotate, deproject, r, cos(phi)
     if spec.bulge:
-        f += 42                              # R, s, g and h polynomials, B, B sigma^2, mass, v_c^2
+        f += 42 if spec.bulge == 1 else 40   # R, s, g and h polynomials, B, B sigma^2, mass, v_c^2
     f += 32 * spec.n_discs                   # exp, B, light sums, phi polynomial, v_c^2
     f += {0: 0, 1: 6, 2: 19}[spec.halo]      # Hernquist / NFW v_c^2
     f += 13                                  # v_int, light-weighted v, sigma, <L/M>
@@ -329,7 +331,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="realistic",
-                    help="realistic (default), tiny, adjoint, stress or uneven (many galaxies)")
+                    help="realistic (default), tiny, adjoint, stress, jaffe or uneven (many galaxies)")
     ap.add_argument("--hmc-steps", type=int, default=0,
                     help="also time one graph-captured leapfrog trajectory of this many steps")
     ap.add_argument("--plain", type=int, default=256, help="number of single-vector calls timed")
@@ -478,7 +480,7 @@ def main():
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
             "frac_of_nonpacked_fp32": round(achieved / PEAK_FP32_NONPACKED, 4),
-            "kernel": "gk::fwd_kernel<1,2,2,0>" if args.workload != "tiny" else "gk::fwd_kernel<1,1,2,0>",
+            "kernel": f"gk::fwd_kernel<{spec.bulge},{spec.n_discs},{spec.halo},0>",
             "flop_per_vector": flop_theta,
             "per_unit": {"lattice_points": n_need, "flop_per_point": flops_per_point(spec),
                          "valid_spaxels": n_valid, "flop_per_spaxel": flops_per_pixel(spec)}}

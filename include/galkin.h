@@ -30,7 +30,8 @@
  *
  * Parameter layout (theta columns), components as configured in the grid:
  *    frame              x0 [px], y0 [px], PA [deg], i [deg]
- *    bulge (Hernquist)  log10 Mb [Msun], Rb [kpc], (M/L)b [Msun/Lsun]
+ *    bulge              log10 Mb [Msun], Rb [kpc], (M/L)b [Msun/Lsun]
+ *                       (Hernquist, Sec. 2.2, or Jaffe, Appendix B)
  *    disc j (1..n)      log10 Mdj [Msun], Rdj [kpc], (M/L)dj, kj
  *    halo               log10 Mh [Msun], then c (NFW) or Rh [kpc] (Hernquist)
  * The galaxy centre is the grid centre ((nx-1)/2, (ny-1)/2) plus (x0, y0);
@@ -51,7 +52,7 @@ enum {
     GK_ESTATE = -4    /* call out of order (e.g. loglike before set_data)    */
 };
 
-enum { GK_BULGE_NONE = 0, GK_BULGE_HERNQUIST = 1 };
+enum { GK_BULGE_NONE = 0, GK_BULGE_HERNQUIST = 1, GK_BULGE_JAFFE = 2 /* Appendix B */ };
 enum { GK_HALO_NONE = 0, GK_HALO_HERNQUIST = 1, GK_HALO_NFW = 2 };
 
 typedef struct gk_grid* gk_grid_t;   /* opaque; owns all device buffers */

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgalkin.so")
 
 GK_OK, GK_EINVAL, GK_ENOMEM, GK_EHIP, GK_ESTATE = 0, -1, -2, -3, -4
-GK_BULGE_NONE, GK_BULGE_HERNQUIST = 0, 1
+GK_BULGE_NONE, GK_BULGE_HERNQUIST, GK_BULGE_JAFFE = 0, 1, 2
 GK_HALO_NONE, GK_HALO_HERNQUIST, GK_HALO_NFW = 0, 1, 2
 
 EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",

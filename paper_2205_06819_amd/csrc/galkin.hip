@@ -211,7 +211,8 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
 
     // --- prologue: tables, zeroed row buffer, row spans
     if (load_tables) {
-        for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = gk_tab_gh[i];
+        const float* tgh = BULGE == 2 ? gk_tab_jgh : gk_tab_gh;     // one bulge kind per grid
+        for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = tgh[i];
         for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
         for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
     }
@@ -422,6 +423,9 @@ __global__ void __launch_bounds__(MULTI_BS) multi_kernel(const FwdArgs* __restri
         GK_MCASE(1, 0, 0) GK_MCASE(1, 0, 1) GK_MCASE(1, 0, 2)
         GK_MCASE(1, 1, 0) GK_MCASE(1, 1, 1) GK_MCASE(1, 1, 2)
         GK_MCASE(1, 2, 0) GK_MCASE(1, 2, 1) GK_MCASE(1, 2, 2)
+        GK_MCASE(2, 0, 0) GK_MCASE(2, 0, 1) GK_MCASE(2, 0, 2)
+        GK_MCASE(2, 1, 0) GK_MCASE(2, 1, 1) GK_MCASE(2, 1, 2)
+        GK_MCASE(2, 2, 0) GK_MCASE(2, 2, 1) GK_MCASE(2, 2, 2)
         GK_MCASE(0, 1, 0) GK_MCASE(0, 1, 1) GK_MCASE(0, 1, 2)
         GK_MCASE(0, 2, 0) GK_MCASE(0, 2, 1) GK_MCASE(0, 2, 2)
 #undef GK_MCASE
@@ -477,8 +481,9 @@ __device__ inline void chain_rule(const double* th, const GridGeom& g, const dou
     int k = 4;
     if (g.bulge) {
         const double Mb = exp10(th[k]), Rb = th[k + 1], ML = th[k + 2];
-        const double Ab = 1.0e-6 * Mb / (2.0 * PI * Rb * Rb * ML);
-        const double Cb = 1.0e-6 * G_KPC * Mb * Mb / (12.0 * PI * Rb * Rb * Rb * ML);
+        const double fa = g.bulge == 2 ? 1.0 : 2.0 * PI, fc = g.bulge == 2 ? 4.0 * PI : 12.0 * PI;
+        const double Ab = 1.0e-6 * Mb / (fa * Rb * Rb * ML);
+        const double Cb = 1.0e-6 * G_KPC * Mb * Mb / (fc * Rb * Rb * Rb * ML);
         const double GMb = G_KPC * Mb;
         gr[k] = (cb[C_AB] * Ab + 2.0 * cb[C_CB] * Cb + cb[C_GMB] * GMb) * LN10;
         gr[k + 1] = -cb[C_INVRB] / (Rb * Rb) - 2.0 * cb[C_AB] * Ab / Rb - 3.0 * cb[C_CB] * Cb / Rb + cb[C_RB];
@@ -549,7 +554,8 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
             for (int q = tid; q < a.stride; q += BS) a.grad[(size_t)b * a.stride + q] = 0.0;
         return;
     }
-    for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = gk_tab_gh[i];
+    const float* tgh = BULGE == 2 ? gk_tab_jgh : gk_tab_gh;
+    for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = tgh[i];
     for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
     for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
     for (int i = tid; i < 64; i += BS) s_gw[i] = a.gw[i];
@@ -761,7 +767,7 @@ static int valid_desc(const gk_grid_desc* d) {
         return fail(GK_EINVAL, "supersample must be odd and in [1, 15] (got %d)", d->supersample);
     if (!(d->psf_sigma_px >= 0.0) || d->psf_sigma_px > 64.0)
         return fail(GK_EINVAL, "psf_sigma_px must be in [0, 64]");
-    if (d->bulge != GK_BULGE_NONE && d->bulge != GK_BULGE_HERNQUIST)
+    if (d->bulge != GK_BULGE_NONE && d->bulge != GK_BULGE_HERNQUIST && d->bulge != GK_BULGE_JAFFE)
         return fail(GK_EINVAL, "unknown bulge kind %d", d->bulge);
     if (d->n_discs < 0 || d->n_discs > 2) return fail(GK_EINVAL, "n_discs must be 0, 1 or 2");
     if (d->halo < GK_HALO_NONE || d->halo > GK_HALO_NFW) return fail(GK_EINVAL, "unknown halo kind %d", d->halo);
@@ -883,6 +889,9 @@ static hipError_t launch_fwd(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, i
     GK_LAUNCH(1, 0, 0) GK_LAUNCH(1, 0, 1) GK_LAUNCH(1, 0, 2)
     GK_LAUNCH(1, 1, 0) GK_LAUNCH(1, 1, 1) GK_LAUNCH(1, 1, 2)
     GK_LAUNCH(1, 2, 0) GK_LAUNCH(1, 2, 1) GK_LAUNCH(1, 2, 2)
+    GK_LAUNCH(2, 0, 0) GK_LAUNCH(2, 0, 1) GK_LAUNCH(2, 0, 2)
+    GK_LAUNCH(2, 1, 0) GK_LAUNCH(2, 1, 1) GK_LAUNCH(2, 1, 2)
+    GK_LAUNCH(2, 2, 0) GK_LAUNCH(2, 2, 1) GK_LAUNCH(2, 2, 2)
     GK_LAUNCH(0, 1, 0) GK_LAUNCH(0, 1, 1) GK_LAUNCH(0, 1, 2)
     GK_LAUNCH(0, 2, 0) GK_LAUNCH(0, 2, 1) GK_LAUNCH(0, 2, 2)
 #undef GK_LAUNCH
@@ -987,7 +996,7 @@ static double band_cost(const gk_grid* g, const LaunchCfg& c, int band) {
     const int nr = std::min(g->d.ny, (by + 1) * c.band_h) - by * c.band_h;
     const int nc = std::min(g->d.nx, (bx + 1) * c.band_w) - bx * c.band_w;
     const double pts = (double)((nr - 1) * s + 2 * pad + 1) * ((nc - 1) * s + 2 * pad + 1);
-    const double ncomp = g->d.bulge + g->d.n_discs + (g->d.halo ? 1 : 0);
+    const double ncomp = (g->d.bulge ? 1 : 0) + g->d.n_discs + (g->d.halo ? 1 : 0);
     return pts * (60.0 + 35.0 * ncomp) + 4.0 * nr * nc * (4.0 * (s * (1 + 3 * pad) + 2 * (2 * pad + 1)));
 }
 
@@ -1325,6 +1334,9 @@ int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, doub
     GK_ALAUNCH(1, 0, 0) GK_ALAUNCH(1, 0, 1) GK_ALAUNCH(1, 0, 2)
     GK_ALAUNCH(1, 1, 0) GK_ALAUNCH(1, 1, 1) GK_ALAUNCH(1, 1, 2)
     GK_ALAUNCH(1, 2, 0) GK_ALAUNCH(1, 2, 1) GK_ALAUNCH(1, 2, 2)
+    GK_ALAUNCH(2, 0, 0) GK_ALAUNCH(2, 0, 1) GK_ALAUNCH(2, 0, 2)
+    GK_ALAUNCH(2, 1, 0) GK_ALAUNCH(2, 1, 1) GK_ALAUNCH(2, 1, 2)
+    GK_ALAUNCH(2, 2, 0) GK_ALAUNCH(2, 2, 1) GK_ALAUNCH(2, 2, 2)
     GK_ALAUNCH(0, 1, 0) GK_ALAUNCH(0, 1, 1) GK_ALAUNCH(0, 1, 2)
     GK_ALAUNCH(0, 2, 0) GK_ALAUNCH(0, 2, 1) GK_ALAUNCH(0, 2, 2)
 #undef GK_ALAUNCH

@@ -6,6 +6,8 @@ The kernels evaluate four universal functions of one argument:
 
 * g(s) and h(s) of the projected Hernquist bulge (paper Sec. 2.2: projected
   density M g / (2 pi R_b^2) and Sigma sigma^2 = G M^2 h / (12 pi R_b^3));
+* the same pair for the Jaffe bulge (Appendix B: M g / R_b^2 and
+  G M^2 h / (4 pi R_b^3));
 * phi(y) = y^2 [I0 K0 - I1 K1](y) of the exponential-disc rotation curve
   (paper Sec. 2.3, read as in Binney & Tremaine: v^2 = (2 G M / R_d) phi(r / 2R_d));
 * m(x) = [ln(1 + x) - x / (1 + x)] / x of the NFW halo (v^2 = G M200 m(r/r_s) / (r_s mu(c))).
@@ -79,6 +81,38 @@ def h_hq_raw(s):
     s2 = s * s
     return ((-3 * s2 * X(s) * (8 * s2 ** 3 - 28 * s2 ** 2 + 35 * s2 - 20) - 24 * s2 ** 3
              + 68 * s2 ** 2 - 65 * s2 + 6) / (2 * (1 - s2) ** 3) - 6 * mp.pi * s)
+
+
+def g_jf_raw(s):
+    s = mp.mpf(s)
+    return 1 / (4 * s) + (1 - (2 - s * s) * X(s)) / (2 * mp.pi * (1 - s * s))
+
+
+def h_jf_raw(s):
+    s = mp.mpf(s)
+    s2 = s * s
+    return (mp.pi / (2 * s) + 11 - mp.mpf(13) / 2 * mp.pi * s - 12 * s2 + 6 * mp.pi * s2 * s
+            - X(s) * (6 - 19 * s2 + 12 * s2 * s2)) / (1 - s2)
+
+
+def g_jf(s):
+    """Jaffe projected density / (M / R_b^2) (Appendix B)."""
+    if abs(mp.mpf(s) - 1) < mp.mpf(10) ** -6:
+        return _near_one(g_jf_raw, s)
+    if mp.mpf(s) > 8:                       # the printed form cancels ~ s^4 at large s
+        with mp.workdps(80 + int(4 * mp.log10(mp.mpf(s)))):
+            return +g_jf_raw(s)
+    return g_jf_raw(s)
+
+
+def h_jf(s):
+    """Jaffe Sigma sigma^2 / (G M^2 / (4 pi R_b^3)) (Appendix B)."""
+    if abs(mp.mpf(s) - 1) < mp.mpf(10) ** -6:
+        return _near_one(h_jf_raw, s)
+    if mp.mpf(s) > 8:
+        with mp.workdps(80 + int(5 * mp.log10(mp.mpf(s)))):
+            return +h_jf_raw(s)
+    return h_jf_raw(s)
 
 
 def phi_disc(y):
@@ -171,15 +205,23 @@ X_LO, X_HI = -24, 8         # NFW x = r / r_s
 def main(out_path):
     g_tab, eg = build_table(g_hq, S_LO, S_HI, "g")
     h_tab, eh = build_table(h_hq, S_LO, S_HI, "h")
+    jg_tab, ejg = build_table(g_jf, S_LO, S_HI, "jaffe g")
+    jh_tab, ejh = build_table(h_jf, S_LO, S_HI, "jaffe h")
     p_tab, ep = build_table(phi_disc, Y_LO, Y_HI, "phi")
     m_tab, em = build_table(m_nfw, X_LO, X_HI, "m")
     # asymptotic tails: s^3 g, s^4 h in w = 1/s on [0, 2^-S_HI]; 4 y phi in 1/y on [0, 2^-Y_HI]
     wg = 2.0 ** -S_HI
     tg = asym_fit(lambda w: g_hq(1 / w) / w ** 3 if w > 0 else mp.pi / 2, wg)
     th = asym_fit(lambda w: h_hq(1 / w) / w ** 4 if w > 0 else mp.mpf(8) / 5, wg)
+    # Jaffe tails: s^3 g and s^4 h in w = 1/s (limits from the closed forms at s = 1e30)
+    jg_inf = g_jf(mp.mpf(10) ** 30) * mp.mpf(10) ** 90
+    jh_inf = h_jf(mp.mpf(10) ** 30) * mp.mpf(10) ** 120
+    tjg = asym_fit(lambda w: g_jf(1 / w) / w ** 3 if w > 0 else jg_inf, wg)
+    tjh = asym_fit(lambda w: h_jf(1 / w) / w ** 4 if w > 0 else jh_inf, wg)
     wy = 2.0 ** -Y_HI
     tp = asym_fit(lambda w: 4 * phi_disc(1 / w) / w if w > 0 else mp.mpf(1), wy)
     for nm, cf, ff, sc, wm in [("g", tg, g_hq, 3, wg), ("h", th, h_hq, 4, wg),
+                               ("jaffe g", tjg, g_jf, 3, wg), ("jaffe h", tjh, h_jf, 4, wg),
                                ("phi", tp, phi_disc, None, wy)]:
         worst = 0.0
         for w in np.linspace(wm / 100, wm, 7):
@@ -192,6 +234,7 @@ def main(out_path):
         print(f"tail {nm}: {cf}  max rel {worst:.2e}", file=sys.stderr)
 
     gh = np.concatenate([g_tab, h_tab], axis=1)          # [npiece, 16]
+    jgh = np.concatenate([jg_tab, jh_tab], axis=1)
 
     def arr(a):
         flat = a.reshape(-1)
@@ -203,7 +246,8 @@ def main(out_path):
     with open(out_path, "w") as fh:
         fh.write("// Generated by gen_tables.py; do not edit.\n")
         fh.write("// Degree-7 polynomials in u in [-1,1] on quarter-octave pieces; see gen_tables.py.\n")
-        fh.write(f"// max relative fit errors: g {eg:.1e}, h {eh:.1e}, phi {ep:.1e}, m {em:.1e}\n")
+        fh.write(f"// max relative fit errors: g {eg:.1e}, h {eh:.1e}, Jaffe g {ejg:.1e}, Jaffe h {ejh:.1e}, "
+                 f"phi {ep:.1e}, m {em:.1e}\n")
         fh.write("#pragma once\n\n")
         fh.write("#ifndef GK_TABLE_QUAL\n#define GK_TABLE_QUAL static const\n#endif\n\n")
         fh.write(f"#define GK_S_ELO ({S_LO})\n#define GK_S_EHI ({S_HI})\n")
@@ -213,11 +257,13 @@ def main(out_path):
         fh.write(f"#define GK_M_NPIECE {m_tab.shape[0]}\n\n")
         fh.write("// g coefficients c0..c7 then h coefficients c0..c7, per piece\n")
         fh.write(f"GK_TABLE_QUAL float gk_tab_gh[{gh.size}] = {{\n{arr(gh)}\n}};\n\n")
+        fh.write("// Jaffe bulge (Appendix B): g then h coefficients per piece, same pieces as gk_tab_gh\n")
+        fh.write(f"GK_TABLE_QUAL float gk_tab_jgh[{jgh.size}] = {{\n{arr(jgh)}\n}};\n\n")
         fh.write(f"GK_TABLE_QUAL float gk_tab_phi[{p_tab.size}] = {{\n{arr(p_tab)}\n}};\n\n")
         fh.write(f"GK_TABLE_QUAL float gk_tab_m[{m_tab.size}] = {{\n{arr(m_tab)}\n}};\n\n")
         fh.write("// tails: s^3 g(s), s^4 h(s) as cubics in w = 1/s for s >= 2^GK_S_EHI;\n")
         fh.write("// 4 y phi(y) as a cubic in w = 1/y for y >= 2^GK_Y_EHI\n")
-        for nm, cf in [("g", tg), ("h", th), ("phi", tp)]:
+        for nm, cf in [("g", tg), ("h", th), ("jg", tjg), ("jh", tjh), ("phi", tp)]:
             fh.write(f"#define GK_TAIL_{nm.upper()}(w) ({cf[0]:.9e}f + (w) * ({cf[1]:.9e}f + (w) * "
                      f"({cf[2]:.9e}f + (w) * {cf[3]:.9e}f)))\n")
 

@@ -80,8 +80,11 @@ __device__ inline TC make_tc(const double* th, const GridGeom& g) {
         const double Mb = exp10(th[k]), Rb = th[k + 1], ML = th[k + 2];
         ok = ok && Rb > 0.0 && ML > 0.0;
         c.invRb = (float)(1.0 / Rb);
-        c.Ab = (float)(1.0e-6 * Mb / (2.0 * PI * Rb * Rb * ML));
-        c.Cb = (float)(1.0e-6 * G_KPC * Mb * Mb / (12.0 * PI * Rb * Rb * Rb * ML));
+        // Hernquist (Sec. 2.2): Sigma = M g / (2 pi Rb^2), Sigma sigma^2 = G M^2 h / (12 pi Rb^3);
+        // Jaffe (Appendix B): Sigma = M g / Rb^2, Sigma sigma^2 = G M^2 h / (4 pi Rb^3)
+        const double fa = g.bulge == 2 ? 1.0 : 2.0 * PI, fc = g.bulge == 2 ? 4.0 * PI : 12.0 * PI;
+        c.Ab = (float)(1.0e-6 * Mb / (fa * Rb * Rb * ML));
+        c.Cb = (float)(1.0e-6 * G_KPC * Mb * Mb / (fc * Rb * Rb * Rb * ML));
         c.GMb = (float)(G_KPC * Mb);
         c.Rb = (float)Rb;
         c.MLb = (float)ML;
@@ -191,7 +194,14 @@ __device__ __forceinline__ float horner8d(const float4 a, const float4 b, float 
     return p;
 }
 
-// Hernquist g(s), h(s) for s >= 1e-6
+// bulge g(s), h(s) for s >= 1e-6 from the staged table (Hernquist, or Jaffe
+// when JF); beyond the table s^3 g and s^4 h are cubics in w = 1/s
+template <bool JF>
+__device__ __forceinline__ float tail_g(float w) { return JF ? GK_TAIL_JG(w) : GK_TAIL_G(w); }
+template <bool JF>
+__device__ __forceinline__ float tail_h(float w) { return JF ? GK_TAIL_JH(w) : GK_TAIL_H(w); }
+
+template <bool JF>
 __device__ __forceinline__ void eval_gh(const float4* __restrict__ T, float s, float& g, float& h) {
     if (s < 4096.0f) {
         float u;
@@ -200,10 +210,11 @@ __device__ __forceinline__ void eval_gh(const float4* __restrict__ T, float s, f
         h = horner8(T[4 * k + 2], T[4 * k + 3], u);
     } else {
         const float w = frcp(s), w3 = w * w * w;
-        g = w3 * GK_TAIL_G(w);
-        h = w3 * w * GK_TAIL_H(w);
+        g = w3 * tail_g<JF>(w);
+        h = w3 * w * tail_h<JF>(w);
     }
 }
+template <bool JF>
 __device__ __forceinline__ void eval_gh_d(const float4* __restrict__ T, float s, float& g, float& h,
                                           float& dg, float& dh) {
     if (s < 4096.0f) {
@@ -217,10 +228,10 @@ __device__ __forceinline__ void eval_gh_d(const float4* __restrict__ T, float s,
     } else {
         // s^3 g = Pg(w), s^4 h = Ph(w), w = 1/s: dg/ds = -w^4 (3 Pg + w Pg'), dh/ds = -w^5 (4 Ph + w Ph')
         const float w = frcp(s), w2 = w * w, w3 = w2 * w;
-        const float pg = GK_TAIL_G(w), ph = GK_TAIL_H(w);
+        const float pg = tail_g<JF>(w), ph = tail_h<JF>(w);
         const float e = 1.0e-3f;                           // tails are cubics; exact slope
-        const float pg1 = (GK_TAIL_G(w + e) - GK_TAIL_G(w - e)) / (2.0f * e);
-        const float ph1 = (GK_TAIL_H(w + e) - GK_TAIL_H(w - e)) / (2.0f * e);
+        const float pg1 = (tail_g<JF>(w + e) - tail_g<JF>(w - e)) / (2.0f * e);
+        const float ph1 = (tail_h<JF>(w + e) - tail_h<JF>(w - e)) / (2.0f * e);
         g = w3 * pg;
         h = w3 * w * ph;
         dg = -w3 * w * (3.0f * pg + w * pg1);
@@ -309,13 +320,14 @@ __device__ __forceinline__ void point_model(const TC& c, const Tabs& T, float du
         const float R = fsqrt(x2 + y2);
         const float sb = fmaxf(R * c.invRb, S_MIN);
         float g, h;
-        eval_gh(T.gh, sb, g, h);
+        eval_gh<BULGE == 2>(T.gh, sb, g, h);
         const float Bb = c.Ab * g;
         Bt = Bb;
         BS = c.Cb * h;
         mass = Bb * c.MLb;
         const float q = r + c.Rb;
-        vc2 = c.GMb * r * frcp(q * q);
+        // Hernquist G M r / (r + Rb)^2; Jaffe G M / (r + Rb) (Appendix B)
+        vc2 = BULGE == 2 ? c.GMb * frcp(q) : c.GMb * r * frcp(q * q);
     }
     // discs: without a bulge, weights are taken relative to the largest disc
     // exponential so that the ratios survive FP32 underflow far out
@@ -385,13 +397,13 @@ __device__ __forceinline__ void point_model_adj(const TC& c, const Tabs& T, floa
         const float sbr = R * c.invRb;
         clamped = !(sbr > S_MIN);
         const float sb = clamped ? S_MIN : sbr;
-        eval_gh_d(T.gh, sb, g, h, dg, dh);
+        eval_gh_d<BULGE == 2>(T.gh, sb, g, h, dg, dh);
         Bb = c.Ab * g;
         Bt = Bb;
         BS = c.Cb * h;
         mass = Bb * c.MLb;
         iqb = frcp(r + c.Rb);
-        vc2 = c.GMb * r * iqb * iqb;
+        vc2 = BULGE == 2 ? c.GMb * iqb : c.GMb * r * iqb * iqb;
     }
     float eref = 0.0f;
     if (!BULGE && NDISC > 0) {
@@ -479,10 +491,17 @@ __device__ __forceinline__ void point_model_adj(const TC& c, const Tabs& T, floa
     float x2b = 0.0f, y2b = 0.0f;
     if (BULGE) {
         const float iq2 = iqb * iqb;
-        ad[C_GMB] = fmaf(vc2b, r * iq2, ad[C_GMB]);
         const float t = vc2b * c.GMb;
-        rb = fmaf(t, iq2 - 2.0f * r * iq2 * iqb, rb);
-        ad[C_RB] = fmaf(t, -2.0f * r * iq2 * iqb, ad[C_RB]);
+        if (BULGE == 2) {
+            // v^2 = GM / q: d/dGM = 1/q; d/dr = d/dRb = -GM / q^2
+            ad[C_GMB] = fmaf(vc2b, iqb, ad[C_GMB]);
+            rb = fmaf(t, -iq2, rb);
+            ad[C_RB] = fmaf(t, -iq2, ad[C_RB]);
+        } else {
+            ad[C_GMB] = fmaf(vc2b, r * iq2, ad[C_GMB]);
+            rb = fmaf(t, iq2 - 2.0f * r * iq2 * iqb, rb);
+            ad[C_RB] = fmaf(t, -2.0f * r * iq2 * iqb, ad[C_RB]);
+        }
         const float Bbb = fmaf(massb, c.MLb, Btb);
         ad[C_MLB] = fmaf(massb, Bb, ad[C_MLB]);
         ad[C_CB] = fmaf(BSb, h, ad[C_CB]);

@@ -1,5 +1,5 @@
 """GPU parity of the many-grid launch (loglike_multi): galaxies of different
-sizes and component sets in one persistent launch give the single-grid
+sizes and component sets in one launch give the single-grid
 results (to FP64 summation order) and the oracle's at each galaxy's truth."""
 import sys
 import zlib
@@ -36,6 +36,7 @@ SPECS = [
     (W.GridSpec(17, 19, 0.3, 5, 0.7, 1, 0, W.HALO_NONE), 2),
     (W.GridSpec(21, 20, 0.2, 3, 0.0, 1, 1, W.HALO_NFW), 4),
     (W.GridSpec(70, 66, 0.12, 3, 1.06, 1, 2, W.HALO_NFW), 3),   # wider than one band
+    (W.GridSpec(26, 28, 0.2, 3, 1.06, W.BULGE_JAFFE, 2, W.HALO_NFW), 4),
 ]
 
 
@@ -70,7 +71,7 @@ def stacked_thetas(specs, truths, stride, seed=7):
 
 
 def test_multi_matches_single_grid_and_oracle(gk):
-    say("[multi] 7 grids, uneven sizes and component sets")
+    say(f"[multi] {len(SPECS)} grids, uneven sizes and component sets")
     grids, truths, datas = build(gk, SPECS)
     stride = max(s.n_params for s, _ in SPECS) + 2
     th_np, offs = stacked_thetas(SPECS, truths, stride)

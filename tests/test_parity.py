@@ -73,6 +73,10 @@ CASES = {
     "nobulge_2d_nohalo": (W.GridSpec(24, 18, 0.25, 1, 1.6, 0, 2, W.HALO_NONE), None, 6),
     "bulge_only_s5": (W.GridSpec(17, 19, 0.3, 5, 0.7, 1, 0, W.HALO_NONE), (7.0, 8.0), 4),
     "no_psf": (W.GridSpec(21, 20, 0.2, 3, 0.0, 1, 1, W.HALO_NFW), None, 4),
+    # Jaffe bulge (Appendix B)
+    "jaffe_2d_nfw": (W.GridSpec(33, 29, 0.15, 3, 1.06, W.BULGE_JAFFE, 2, W.HALO_NFW), (14.0, 12.0), 6),
+    "jaffe_only_s5": (W.GridSpec(19, 17, 0.25, 5, 0.7, W.BULGE_JAFFE, 0, W.HALO_NONE), None, 4),
+    "jaffe_1d_hq_s1": (W.GridSpec(30, 26, 0.3, 1, 1.3, W.BULGE_JAFFE, 1, W.HALO_HERNQUIST), None, 6),
 }
 
 
@@ -193,7 +197,8 @@ def check_grad(got, ref, tag):
 
 @pytest.mark.parametrize("name,n", [("tiny", 4), ("ragged_s3_2d_hq", 3), ("nobulge_1d", 3),
                                     ("nobulge_2d_nohalo", 3), ("bulge_only_s5", 3), ("no_psf", 3),
-                                    ("realistic", 2)])
+                                    ("realistic", 2), ("jaffe_2d_nfw", 3), ("jaffe_only_s5", 2),
+                                    ("jaffe_1d_hq_s1", 2)])
 def test_gradient_matches_oracle(gk, name, n):
     spec, data, err, thetas = make_case(name)
     thetas = thetas[:n]

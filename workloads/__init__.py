@@ -175,7 +175,7 @@ SEED0 = 20220505
 
 
 def workload(name: str) -> Workload:
-    """The benchmark workloads, by name: tiny, realistic, adjoint, stress."""
+    """The benchmark workloads, by name: tiny, realistic, adjoint, stress, jaffe."""
     if name == "tiny":
         spec = GridSpec(40, 40, PK_50MPC, 1, 1.5, BULGE_HERNQUIST, 1, HALO_NFW)
         return Workload(name, spec, 64, None, SEED0 + 0)
@@ -185,6 +185,10 @@ def workload(name: str) -> Workload:
     if name == "adjoint":
         spec = GridSpec(100, 100, PK_50MPC, 3, SIGMA_FWHM_2P5, BULGE_HERNQUIST, 2, HALO_NFW)
         return Workload(name, spec, 4096, None, SEED0 + 3, gradient=True)
+    if name == "jaffe":
+        # the realistic IFU cube with the Appendix-B (Jaffe) bulge
+        spec = GridSpec(80, 80, PK_50MPC, 3, SIGMA_FWHM_2P5, BULGE_JAFFE, 2, HALO_NFW)
+        return Workload(name, spec, 1024, (38.0, 33.6), SEED0 + 5)
     if name == "stress":
         spec = GridSpec(300, 300, PK_50MPC, 5, SIGMA_FWHM_4, BULGE_HERNQUIST, 2, HALO_NFW)
         return Workload(name, spec, 8192, None, SEED0 + 4, gradient=True)
