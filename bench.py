@@ -383,6 +383,54 @@ def bench_nested(args):
 
 
 # ----------------------------------------------------------------------------
+# data preparation (colour-M/L maps): an HBM-bound elementwise kernel
+# ----------------------------------------------------------------------------
+def bench_prep(args):
+    import torch
+    import paper_2205_06819_amd as gk
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = 4096 * 4096
+    g = torch.Generator(device=dev).manual_seed(3)
+    mb = 15 + 7 * torch.rand(n, device=dev, generator=g)
+    mg = mb - 1.8 * torch.rand(n, device=dev, generator=g) + 0.2
+    eb = 0.01 + 0.3 * torch.rand(n, device=dev, generator=g)
+    eg = 0.01 + 0.3 * torch.rand(n, device=dev, generator=g)
+    ml = torch.empty_like(mb)
+    err = torch.empty_like(mb)
+    stream = torch.cuda.current_stream()
+
+    def call():
+        gk._check(gk._lib.ml_from_colour(mb.data_ptr(), mg.data_ptr(), eb.data_ptr(), eg.data_ptr(), n,
+                                         -0.70, 0.89, 0.07, ml.data_ptr(), err.data_ptr(), gk._stream(stream)))
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    byts = 24 * n                                  # 4 float32 maps in, 2 out
+    gbs = byts / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "likelihood evals/s and gradient evals/s (params×spaxels/s), batched vs plain",
+        "value": round(n / (ms * 1e-3), 1), "unit": "pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "colour-M/L data preparation (Sec. 2.5.1 relation, Appendix C errors) on a "
+                               "4096x4096 map", "pixels": n},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(gbs / 8000.0, 4), "traffic": None, "kernel": "gk::ml_colour_kernel4",
+                     "bytes_per_launch": byts},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ----------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,7 +438,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="realistic",
                     help="realistic (default), tiny, adjoint, stress, jaffe, uneven (many galaxies) "
-                         "or nested (the nested sampler driving the likelihood)")
+                         "nested (the nested sampler driving the likelihood) or prep (colour-M/L maps)")
     ap.add_argument("--hmc-steps", type=int, default=0,
                     help="also time one graph-captured leapfrog trajectory of this many steps")
     ap.add_argument("--plain", type=int, default=256, help="number of single-vector calls timed")
@@ -413,6 +461,8 @@ def main():
         return bench_uneven(args)
     if args.workload == "nested":
         return bench_nested(args)
+    if args.workload == "prep":
+        return bench_prep(args)
 
     import torch
     import workloads as W

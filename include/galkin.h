@@ -147,6 +147,26 @@ int hmc_leapfrog(gk_grid_t grid, double* theta, double* momentum, const double* 
 int loglike_multi(const gk_grid_t* grids, int n_gal, const double* theta, const int* theta_offset,
                   int stride, double* logL, double* grad, void* hip_stream);
 
+/* Data preparation (run once per galaxy, before set_data).
+ *
+ * Colour-M/L relation (Sec. 2.5.1, eq:ML-color; errors as in Appendix C):
+ *   ml[i]  = 10^(a + b (m_beta[i] - m_gamma[i]))
+ *   err[i] = ml[i] ln(10) sqrt(b^2 (dm_beta[i]^2 + dm_gamma[i]^2) + sigma_a^2)
+ * with sigma_a the relation's scatter in dex.  All arrays are float32 device
+ * memory of n pixels (any layout, e.g. [ny][nx]); pixels with a non-finite
+ * magnitude or error get ml = NaN and err = 0, which set_data treats as
+ * masked.  Asynchronous on the stream. */
+int ml_from_colour(const float* m_beta, const float* m_gamma, const float* dm_beta, const float* dm_gamma,
+                   int n, double a, double b, double sigma_a, float* ml, float* err, void* hip_stream);
+
+/* Surface-brightness error model (Sec. 3, data): a relative error plus a
+ * constant systematic floor set by the faintest pixel, added in quadrature:
+ *   err[i] = sqrt((rel B[i])^2 + (floor_frac min B)^2)
+ * where min B is over pixels with finite B > 0; other pixels get err = 0
+ * (masked).  float32 device arrays of n pixels; one workgroup;
+ * asynchronous on the stream. */
+int brightness_errors(const float* B, int n, double rel, double floor_frac, float* err, void* hip_stream);
+
 /* Launch shape used for batches of size >= batch_min: a band of band_h x
  * band_w pixels per workgroup (band_h, band_w >= 1) and steps pixel rows per
  * model phase (1..4; 0 = chosen from the lattice factor).  The autotuner sets

@@ -27,7 +27,8 @@ GK_BULGE_NONE, GK_BULGE_HERNQUIST, GK_BULGE_JAFFE = 0, 1, 2
 GK_HALO_NONE, GK_HALO_HERNQUIST, GK_HALO_NFW = 0, 1, 2
 
 EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",
-           "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "last_error")
+           "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "ml_from_colour",
+           "brightness_errors", "last_error")
 
 
 class GalkinError(RuntimeError):
@@ -61,6 +62,8 @@ def _load() -> ctypes.CDLL:
     lib.set_launch_shape.argtypes = [vp, i, i, i, i]
     lib.hmc_leapfrog.argtypes = [vp, vp, vp, vp, d, i, i, i, vp, vp, vp]
     lib.loglike_multi.argtypes = [vp, i, vp, vp, i, vp, vp, vp]
+    lib.ml_from_colour.argtypes = [vp, vp, vp, vp, i, d, d, d, vp, vp, vp]
+    lib.brightness_errors.argtypes = [vp, i, d, d, vp, vp]
     lib.last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "last_error":
@@ -208,6 +211,36 @@ def loglike_multi(handles, theta: torch.Tensor, theta_offset, out: Optional[torc
     _check(_lib.loglike_multi(hs, n, theta.data_ptr(), offs.ctypes.data, theta.stride(0), out.data_ptr(),
                               _ptr(grad), _stream(stream)))
     return out
+
+
+def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32):
+        raise ValueError(f"{name} must be a float32 CUDA tensor")
+    return t.contiguous()
+
+
+def ml_from_colour(m_beta, m_gamma, dm_beta, dm_gamma, a: float, b: float, sigma_a: float,
+                   stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """M/L map and its error from two magnitude maps (see include/galkin.h)."""
+    xs = [_dev_f32(t, nm) for t, nm in ((m_beta, "m_beta"), (m_gamma, "m_gamma"),
+                                        (dm_beta, "dm_beta"), (dm_gamma, "dm_gamma"))]
+    n = xs[0].numel()
+    if any(x.numel() != n for x in xs):
+        raise ValueError("magnitude maps differ in size")
+    ml = torch.empty_like(xs[0])
+    err = torch.empty_like(xs[0])
+    _check(_lib.ml_from_colour(*[x.data_ptr() for x in xs], n, float(a), float(b), float(sigma_a),
+                               ml.data_ptr(), err.data_ptr(), _stream(stream)))
+    return ml, err
+
+
+def brightness_errors(B, rel: float = 0.05, floor_frac: float = 0.1, stream=None) -> torch.Tensor:
+    """Surface-brightness errors: relative part plus a floor from the faintest pixel."""
+    B = _dev_f32(B, "B")
+    err = torch.empty_like(B)
+    _check(_lib.brightness_errors(B.data_ptr(), B.numel(), float(rel), float(floor_frac), err.data_ptr(),
+                                  _stream(stream)))
+    return err
 
 
 def set_launch_shape(handle: int, batch_min: int, band_h: int, band_w: int, steps: int = 0) -> None:

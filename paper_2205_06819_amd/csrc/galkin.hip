@@ -1436,3 +1436,126 @@ int loglike_multi(const gk_grid_t* grids, int n_gal, const double* theta, const 
 }
 
 }  // extern "C"
+
+// ============================================================================
+// data preparation: colour-M/L maps and the surface-brightness error model
+// ============================================================================
+namespace gk {
+
+__global__ void __launch_bounds__(256) ml_colour_kernel(const float* __restrict__ mb, const float* __restrict__ mg,
+                                                        const float* __restrict__ dmb,
+                                                        const float* __restrict__ dmg, int n, float a, float b,
+                                                        float s2, float* __restrict__ ml, float* __restrict__ err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = mb[i], y = mg[i], ex = dmb[i], ey = dmg[i];
+    const bool ok = isfinite(x) && isfinite(y) && isfinite(ex) && isfinite(ey);
+    // log10 (M/L) = a + b (m_beta - m_gamma); its error adds the magnitude errors
+    // and the relation's scatter in quadrature
+    const float lg = fmaf(b, x - y, a);
+    const float m = exp10f(lg);
+    const float el = sqrtf(fmaf(b * b, fmaf(ex, ex, ey * ey), s2));
+    ml[i] = ok ? m : __int_as_float(0x7fc00000);
+    err[i] = ok ? m * 2.302585093f * el : 0.0f;
+}
+
+__device__ __forceinline__ void ml_colour_one(float x, float y, float ex, float ey, float a, float b, float s2,
+                                              float& m_out, float& e_out) {
+    const bool ok = isfinite(x) && isfinite(y) && isfinite(ex) && isfinite(ey);
+    const float m = exp10f(fmaf(b, x - y, a));
+    const float el = sqrtf(fmaf(b * b, fmaf(ex, ex, ey * ey), s2));
+    m_out = ok ? m : __int_as_float(0x7fc00000);
+    e_out = ok ? m * 2.302585093f * el : 0.0f;
+}
+
+// four pixels per thread through 16-byte loads and stores (all six arrays
+// 16-byte aligned); the last n % 4 pixels by the first threads, one each
+__global__ void __launch_bounds__(256) ml_colour_kernel4(const float4* __restrict__ mb, const float4* __restrict__ mg,
+                                                         const float4* __restrict__ dmb,
+                                                         const float4* __restrict__ dmg, int n, float a, float b,
+                                                         float s2, float4* __restrict__ ml, float4* __restrict__ err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n4 = n >> 2;
+    if (i < n4) {
+        const float4 x = mb[i], y = mg[i], ex = dmb[i], ey = dmg[i];
+        float4 m, e;
+        ml_colour_one(x.x, y.x, ex.x, ey.x, a, b, s2, m.x, e.x);
+        ml_colour_one(x.y, y.y, ex.y, ey.y, a, b, s2, m.y, e.y);
+        ml_colour_one(x.z, y.z, ex.z, ey.z, a, b, s2, m.z, e.z);
+        ml_colour_one(x.w, y.w, ex.w, ey.w, a, b, s2, m.w, e.w);
+        ml[i] = m;
+        err[i] = e;
+    }
+    const int t = 4 * n4 + i;
+    if (i < (n & 3)) {
+        const float* fmb = (const float*)mb;
+        const float* fmg = (const float*)mg;
+        const float* fdb = (const float*)dmb;
+        const float* fdg = (const float*)dmg;
+        ml_colour_one(fmb[t], fmg[t], fdb[t], fdg[t], a, b, s2, ((float*)ml)[t], ((float*)err)[t]);
+    }
+}
+
+// one workgroup: the smallest positive finite B, then every pixel's error
+__global__ void __launch_bounds__(1024) b_err_kernel(const float* __restrict__ B, int n, float rel, float floor_frac,
+                                                     float* __restrict__ err) {
+    __shared__ float s_min[16];
+    const int tid = threadIdx.x, BS = blockDim.x;
+    float mn = INFINITY;
+    for (int i = tid; i < n; i += BS) {
+        const float v = B[i];
+        if (isfinite(v) && v > 0.0f) mn = fminf(mn, v);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_down(mn, o, 64));
+    if ((tid & 63) == 0) s_min[tid >> 6] = mn;
+    __syncthreads();
+    mn = INFINITY;
+    for (int w = 0; w < (BS + 63) / 64; ++w) mn = fminf(mn, s_min[w]);
+    const float sys = isfinite(mn) ? floor_frac * mn : 0.0f;
+    for (int i = tid; i < n; i += BS) {
+        const float v = B[i];
+        const float r = rel * v;
+        err[i] = (isfinite(v) && v > 0.0f) ? sqrtf(fmaf(r, r, sys * sys)) : 0.0f;
+    }
+}
+
+}  // namespace gk
+
+extern "C" {
+
+int ml_from_colour(const float* m_beta, const float* m_gamma, const float* dm_beta, const float* dm_gamma, int n,
+                   double a, double b, double sigma_a, float* ml, float* err, void* stream) {
+    if (n < 0) return fail(GK_EINVAL, "n must be >= 0");
+    if (n == 0) return GK_OK;
+    if (!m_beta || !m_gamma || !dm_beta || !dm_gamma || !ml || !err) return fail(GK_EINVAL, "NULL pointer");
+    if (!std::isfinite(a) || !std::isfinite(b) || !(sigma_a >= 0.0)) return fail(GK_EINVAL, "bad a, b or sigma_a");
+    auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    const float fa = (float)a, fb = (float)b, s2 = (float)(sigma_a * sigma_a);
+    if (al16(m_beta) && al16(m_gamma) && al16(dm_beta) && al16(dm_gamma) && al16(ml) && al16(err)) {
+        const int n4 = std::max(n >> 2, n & 3);
+        hipLaunchKernelGGL(ml_colour_kernel4, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           (const float4*)m_beta, (const float4*)m_gamma, (const float4*)dm_beta,
+                           (const float4*)dm_gamma, n, fa, fb, s2, (float4*)ml, (float4*)err);
+    } else {
+        hipLaunchKernelGGL(ml_colour_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           m_beta, m_gamma, dm_beta, dm_gamma, n, fa, fb, s2, ml, err);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GK_EHIP, "colour-M/L launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
+}
+
+int brightness_errors(const float* B, int n, double rel, double floor_frac, float* err, void* stream) {
+    if (n < 0) return fail(GK_EINVAL, "n must be >= 0");
+    if (n == 0) return GK_OK;
+    if (!B || !err) return fail(GK_EINVAL, "NULL pointer");
+    if (!(rel >= 0.0) || !(floor_frac >= 0.0)) return fail(GK_EINVAL, "rel and floor_frac must be >= 0");
+    hipLaunchKernelGGL(b_err_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, B, n, (float)rel,
+                       (float)floor_frac, err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GK_EHIP, "error-model launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
+}
+
+}  // extern "C"

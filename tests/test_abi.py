@@ -61,6 +61,10 @@ def test_argument_errors_without_device():
     offs = (ctypes.c_int * 3)(0, 1, 2)
     assert lib.loglike_multi(nulls, 2, None, offs, 13, None, None, None) == gk.GK_EINVAL
     assert "NULL" in gk.last_error()
+    assert lib.ml_from_colour(None, None, None, None, 4, 0.0, 1.0, 0.1, None, None, None) == gk.GK_EINVAL
+    assert lib.ml_from_colour(None, None, None, None, 0, 0.0, 1.0, 0.1, None, None, None) == gk.GK_OK
+    assert lib.brightness_errors(None, 4, 0.05, 0.1, None, None) == gk.GK_EINVAL
+    assert lib.brightness_errors(None, -1, 0.05, 0.1, None, None) == gk.GK_EINVAL
 
 
 def test_binding_has_no_cpu_fallback():
