@@ -254,8 +254,23 @@ def convolve_lattice(spec: GridSpec, f: np.ndarray) -> np.ndarray:
 
 
 def psf_maps(spec: GridSpec, theta) -> np.ndarray:
-    """[4, ny, nx] PSF-averaged (B, v, sigma, <L/M>) at every pixel centre."""
-    return convolve_lattice(spec, model_lattice(spec, theta))
+    """[4, ny, nx] PSF-averaged (B, v, sigma, <L/M>) at every pixel centre.
+
+    psf_mode 0 (Sec. 3.1): each of the four model maps is averaged over the
+    PSF.  psf_mode 1 (luminosity-weighted moments): the PSF averages the
+    light B, the first moment B v, the second moment B (sigma^2 + v^2) and
+    the mass density B / <L/M>; the observed velocity is their ratio to the
+    averaged light, the dispersion the square root of the second moment minus
+    v^2, and <L/M> the averaged light over the averaged mass."""
+    f = model_lattice(spec, theta)
+    if getattr(spec, "psf_mode", 0) == 0:
+        return convolve_lattice(spec, f)
+    B, V, S, LM = f
+    q = convolve_lattice(spec, np.stack([B, B * V, B * (S * S + V * V), B / LM]))
+    v = q[1] / q[0]
+    s2 = q[2] / q[0] - v * v
+    sig = np.sqrt(np.where(np.real(s2) > 0, s2, 0.0 * s2))
+    return np.stack([q[0], v, sig, q[0] / q[3]])
 
 
 def psf_pixels(spec: GridSpec, theta, pixels) -> np.ndarray:
@@ -269,9 +284,16 @@ def psf_pixels(spec: GridSpec, theta, pixels) -> np.ndarray:
     offs = np.array([(a / s, b / s) for a, b, _ in taps])
     wts = np.array([w for _, _, w in taps])
     out = np.zeros((4, len(pixels)))
+    lw = getattr(spec, "psf_mode", 0) == 1
     for n, (i, j) in enumerate(pixels):
         vals = point_model(spec, theta, i + offs[:, 0], j + offs[:, 1])
-        out[:, n] = vals @ wts / W
+        if lw:          # luminosity-weighted moments, combined as in psf_maps
+            B, V, S, LM = vals
+            q = np.stack([B, B * V, B * (S * S + V * V), B / LM]) @ wts / W
+            v = q[1] / q[0]
+            out[:, n] = [q[0], v, math.sqrt(max(q[2] / q[0] - v * v, 0.0)), q[0] / q[3]]
+        else:
+            out[:, n] = vals @ wts / W
     return out
 
 

@@ -293,3 +293,45 @@ def test_jaffe_bulge_circular_velocity_enters_vint():
     Bb = 1e-6 * Mb * S.jf_g(s) / Rb ** 2 / p["MLb"]
     BbS2 = 1e-6 * M.G_KPC * Mb ** 2 * S.jf_h(s) / (4 * math.pi * Rb ** 3 * p["MLb"])
     np.testing.assert_allclose(out[2] ** 2, (BbS2 + Bd * (vb2 + vd2) / 3) / (Bb + Bd), rtol=1e-11)
+
+
+# --- luminosity-weighted PSF moments (psf_mode 1) ------------------------------
+def _lw(spec):
+    import dataclasses
+    return dataclasses.replace(spec, psf_mode=W.PSF_LUMINOSITY)
+
+
+def test_lw_moments_reduce_to_maps_without_psf():
+    spec = spec_small(psf_sigma_px=0.0)
+    th = theta_for(spec)
+    np.testing.assert_allclose(M.psf_maps(_lw(spec), th), M.psf_maps(spec, th), rtol=1e-12, atol=1e-12)
+
+
+def test_lw_moments_conserve_light_momentum_energy_and_mass():
+    # s = 1 and a source negligible in the pad band: the PSF moves light around
+    # but conserves the totals of B, B v, B (sigma^2 + v^2) and the mass
+    spec = _lw(W.GridSpec(41, 41, 0.2, 1, 1.3, W.BULGE_NONE, 1, W.HALO_NFW))
+    th = np.array([0.2, -0.1, 20.0, 40.0, 10.0, 0.15, 1.0, 0.5, 11.5, 8.0])
+    f = M.model_lattice(spec, th)
+    _, _, pad = M.stencil(spec)
+    B, V, S, LM = (x[pad:pad + spec.ny, pad:pad + spec.nx] for x in f)
+    F = M.psf_maps(spec, th)
+    assert F[0].sum() == pytest.approx(B.sum(), rel=1e-9)
+    assert (F[0] * F[1]).sum() == pytest.approx((B * V).sum(), rel=1e-8, abs=1e-9 * np.abs(B * V).sum())
+    assert (F[0] * (F[2] ** 2 + F[1] ** 2)).sum() == pytest.approx((B * (S * S + V * V)).sum(), rel=1e-9)
+    assert (F[0] / F[3]).sum() == pytest.approx((B / LM).sum(), rel=1e-9)
+
+
+def test_lw_alg1_equals_shared_lattice():
+    spec = _lw(spec_small(nx=7, ny=6))
+    th = theta_for(spec)
+    np.testing.assert_allclose(M.psf_maps_alg1(spec, th), M.psf_maps(spec, th), rtol=1e-11, atol=1e-12)
+
+
+def test_lw_dispersion_includes_unresolved_rotation():
+    # under a PSF the luminosity-weighted dispersion exceeds the light-weighted
+    # average of sigma where the velocity field has a gradient
+    spec = spec_small(nx=15, ny=15, psf_sigma_px=1.5)
+    th = theta_for(spec, k1=0.9, k2=0.9)
+    F0, F1 = M.psf_maps(spec, th), M.psf_maps(_lw(spec), th)
+    assert np.median(F1[2] - F0[2]) > 0

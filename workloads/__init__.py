@@ -35,6 +35,7 @@ import numpy as np
 
 # Components
 BULGE_NONE, BULGE_HERNQUIST, BULGE_JAFFE = 0, 1, 2
+PSF_MAPS, PSF_LUMINOSITY = 0, 1
 HALO_NONE, HALO_HERNQUIST, HALO_NFW = 0, 1, 2
 
 ARCSEC_PER_RAD = 180.0 * 3600.0 / math.pi
@@ -57,6 +58,7 @@ class GridSpec:
     n_discs: int = 1
     halo: int = HALO_NFW
     hubble_h: float = 0.7
+    psf_mode: int = 0         # PSF_MAPS (each map averaged) or PSF_LUMINOSITY (moments)
 
     @property
     def n_params(self) -> int:
