@@ -54,6 +54,7 @@ enum {
 
 enum { GK_BULGE_NONE = 0, GK_BULGE_HERNQUIST = 1, GK_BULGE_JAFFE = 2 /* Appendix B */ };
 enum { GK_HALO_NONE = 0, GK_HALO_HERNQUIST = 1, GK_HALO_NFW = 2 };
+enum { GK_PSF_MAPS = 0, GK_PSF_LUMINOSITY = 1 };
 
 typedef struct gk_grid* gk_grid_t;   /* opaque; owns all device buffers */
 
@@ -69,6 +70,10 @@ typedef struct {
     int    n_discs;        /* 0, 1 or 2 exponential discs (Sec. 2.3)            */
     int    halo;           /* GK_HALO_*                                         */
     double hubble_h;       /* NFW: M200 at 200 rho_crit(H0 = 100 h); e.g. 0.7   */
+    int    psf_mode;       /* GK_PSF_MAPS: each model map averaged over the PSF */
+                           /* (Sec. 3.1); GK_PSF_LUMINOSITY: the PSF averages   */
+                           /* B, B v, B (sigma^2 + v^2) and the mass density,   */
+                           /* and v, sigma, M/L follow from their ratios        */
 } gk_grid_desc;
 
 /* Create a grid handle on the current HIP device.  Allocates every device

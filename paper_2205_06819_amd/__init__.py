@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libgalkin.so")
 GK_OK, GK_EINVAL, GK_ENOMEM, GK_EHIP, GK_ESTATE = 0, -1, -2, -3, -4
 GK_BULGE_NONE, GK_BULGE_HERNQUIST, GK_BULGE_JAFFE = 0, 1, 2
 GK_HALO_NONE, GK_HALO_HERNQUIST, GK_HALO_NFW = 0, 1, 2
+GK_PSF_MAPS, GK_PSF_LUMINOSITY = 0, 1
 
 EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",
            "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "ml_from_colour",
@@ -41,7 +42,7 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("pixel_kpc", ctypes.c_double),
                 ("supersample", ctypes.c_int), ("psf_sigma_px", ctypes.c_double),
                 ("bulge", ctypes.c_int), ("n_discs", ctypes.c_int), ("halo", ctypes.c_int),
-                ("hubble_h", ctypes.c_double)]
+                ("hubble_h", ctypes.c_double), ("psf_mode", ctypes.c_int)]
 
 
 def _load() -> ctypes.CDLL:
@@ -94,7 +95,7 @@ def make_desc(spec) -> GridDesc:
     """GridDesc from any object with the descriptor's attribute names."""
     return GridDesc(int(spec.nx), int(spec.ny), float(spec.pixel_kpc), int(spec.supersample),
                     float(spec.psf_sigma_px), int(spec.bulge), int(spec.n_discs), int(spec.halo),
-                    float(getattr(spec, "hubble_h", 0.7)))
+                    float(getattr(spec, "hubble_h", 0.7)), int(getattr(spec, "psf_mode", 0)))
 
 
 # --- C-ABI names -------------------------------------------------------------

@@ -69,12 +69,14 @@ constexpr int RS_CAP = 16;      // lattice rows per model phase
 constexpr int GSUB_CAP = 4;     // pixel-row steps per model phase
 
 struct Layout {                 // LDS carve-up, identical on host and device
-    int tab, rows, red, rows_lo, rows_start, stage, total_bytes;
+    int tab, rows, red, rows_lo, rows_start, stage, fin, total_bytes;
 };
 
 __host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
 
-__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int band_h) {
+// nfin: floats of the per-step exchange buffer of the luminosity-weighted
+// mode (0 otherwise)
+__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int band_h, int nfin) {
     Layout L;
     int off = 0;                                   // in 4-byte words
     L.rows = off;       off += rows * 4 * xw;
@@ -84,6 +86,7 @@ __host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int ba
     L.rows_start = off; off += nfrm + 1 + RS_CAP;  // padded: phase lookups read ahead
     off = (off + 1) & ~1;
     L.stage = off;      off += 2 * band_h + 32;    // row spans and stencil half-widths
+    L.fin = off;        off += nfin;
     // the tables last, at a launch-dependent offset: a table lookup is then one
     // base add and four reads with immediate offsets
     off = (off + 3) & ~3;
@@ -185,12 +188,13 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     const int ubase = c0 * s + hs;                  // lattice column of local column 0
     const int nfrm = nfr_max(a.band_h, s, pad);
     const int RS = a.gsub * s;
-    const Layout L = make_layout(RS, a.xw, nfrm, a.band_h);
+    const Layout L = make_layout(RS, a.xw, nfrm, a.band_h, G.lw ? 8 * a.gsub * a.band_w : 0);
     float* s_tab = smem + L.tab;
     float* s_rows = smem + L.rows;
     double* s_red = (double*)(smem + L.red);
     int* s_lo = (int*)(smem + L.rows_lo);
     int* s_start = (int*)(smem + L.rows_start);
+    float* s_fin = smem + L.fin;                    // [2][gsub][4][band_w] (luminosity-weighted mode)
     const int XW = a.xw;
     const int D = a.D;
 
@@ -310,10 +314,17 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
             float fB, fV, fS, fL;
             point_model<BULGE, NDISC, HALO>(tc, T, du, dv, fB, fV, fS, fL);
             float* row = s_rows + lr * 4 * XW + x;
-            row[0] = fB;
-            row[XW] = fV;
-            row[2 * XW] = fS;
-            row[3 * XW] = fL;
+            if (G.lw) {         // light, first and second velocity moments, mass
+                row[0] = fB;
+                row[XW] = fB * fV;
+                row[2 * XW] = fB * fmaf(fS, fS, fV * fV);
+                row[3 * XW] = fB * frcp(fL);
+            } else {
+                row[0] = fB;
+                row[XW] = fV;
+                row[2 * XW] = fS;
+                row[3 * XW] = fL;
+            }
         }
         __syncthreads();
         // ---- stencil phase: per (map, column) pair, in registers
@@ -336,7 +347,9 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
                 }
 #undef GK_SUB
                 const int jj = q - D;                   // pixel row completed by this step
-                if (jj >= 0) {
+                if (jj >= 0 && G.lw) {
+                    if (pact) s_fin[(k * 4 + pm) * a.band_w + pc] = acc[D] * invW;
+                } else if (jj >= 0) {
                     const float F = acc[D] * invW;
                     const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
                     if (MODE == MODE_MAPS) {
@@ -353,6 +366,72 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
                         }
                         if (MODE == MODE_FBAR && pact) a.fbar[mapoff + pix] = gbar;
                     }
+                }
+            }
+        }
+        if (G.lw) {
+            // luminosity-weighted moments: every pixel's four PSF moments are in
+            // s_fin; each (map, column) thread forms its own observable from them
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < GSUB_CAP; ++k) {
+                if (k >= a.gsub) break;
+                const int jj = q0 + k - D;
+                if (jj < 0 || q0 + k >= Q) continue;
+                const float* fk = s_fin + k * 4 * a.band_w + pc;
+                const float F0 = fk[0], F1 = fk[a.band_w], F2 = fk[2 * a.band_w], F3 = fk[3 * a.band_w];
+                const float i0 = frcp(F0);
+                const float v = F1 * i0;
+                const float s2 = fmaf(F2, i0, -v * v);
+                const float sg = s2 > 0.0f ? fsqrt(s2) : 0.0f;
+                const float obs = pm == 0 ? F0 : pm == 1 ? v : pm == 2 ? sg : F3 * i0;   // B, v, sigma, M/L
+                const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
+                if (MODE == MODE_MAPS) {
+                    if (pact) a.maps[mapoff + pix] = obs;
+                } else {
+                    const float iv = pi[k];
+                    float ob = 0.0f;                    // d logL / d observable
+                    if (iv > 0.0f) {
+                        const float res = obs - pv[k];
+                        chi2 += (double)res * (double)res * (double)iv;
+                        ob = -iv * res;
+                    }
+                    // the clamped threads share an active thread's slot: only the owner writes
+                    if (MODE == MODE_FBAR && pact) s_fin[(4 * a.gsub + k * 4 + pm) * a.band_w + pc] = ob;
+                }
+            }
+            if (MODE == MODE_FBAR) {
+                // d logL / d F_m through v = F1/F0, sigma = sqrt(F2/F0 - v^2), M/L = F3/F0
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < GSUB_CAP; ++k) {
+                    if (k >= a.gsub) break;
+                    const int jj = q0 + k - D;
+                    if (jj < 0 || q0 + k >= Q) continue;
+                    const float* fk = s_fin + k * 4 * a.band_w + pc;
+                    const float* ok_ = s_fin + (4 * a.gsub + k * 4) * a.band_w + pc;
+                    const float F0 = fk[0], F1 = fk[a.band_w], F2 = fk[2 * a.band_w], F3 = fk[3 * a.band_w];
+                    const float o0 = ok_[0], o1 = ok_[a.band_w], o2 = ok_[2 * a.band_w], o3 = ok_[3 * a.band_w];
+                    const float i0 = frcp(F0);
+                    const float v = F1 * i0;
+                    const float s2 = fmaf(F2, i0, -v * v);
+                    const float sg = s2 > 0.0f ? fsqrt(s2) : 0.0f;
+                    const float hs2 = sg > 0.0f ? 0.5f * frcp(sg) : 0.0f;          // d sigma / d s2
+                    // s2 = F2/F0 - F1^2/F0^2
+                    const float ds2_0 = (-F2 + 2.0f * F1 * v) * i0 * i0;
+                    const float ds2_1 = -2.0f * v * i0;
+                    const float ds2_2 = i0;
+                    float gbar;
+                    if (pm == 0)
+                        gbar = o0 - o1 * v * i0 + o2 * hs2 * ds2_0 - o3 * F3 * i0 * i0;
+                    else if (pm == 1)
+                        gbar = o1 * i0 + o2 * hs2 * ds2_1;
+                    else if (pm == 2)
+                        gbar = o2 * hs2 * ds2_2;
+                    else
+                        gbar = o3 * i0;
+                    const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
+                    if (pact) a.fbar[mapoff + pix] = gbar;
                 }
             }
         }
@@ -636,7 +715,18 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
         }
         const float du = (float)(ubase + x - tc.Ui) - tc.Uf;
         const float dv = (float)(vlo + r - tc.Vi) - tc.Vf;
-        point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, f.x * invW, f.y * invW, f.z * invW, f.w * invW, ad);
+        float4 fo = make_float4(f.x * invW, f.y * invW, f.z * invW, f.w * invW);
+        if (G.lw) {
+            // the lattice carries (B, B v, B (sigma^2 + v^2), B / <L/M>): map their
+            // adjoints to those of (B, v, sigma, <L/M>) at this point
+            float pB, pV, pS, pL;
+            point_model<BULGE, NDISC, HALO>(tc, T, du, dv, pB, pV, pS, pL);
+            const float il = frcp(pL);
+            fo = make_float4(fo.x + fo.y * pV + fo.z * fmaf(pS, pS, pV * pV) + fo.w * il,
+                             fmaf(fo.y, pB, 2.0f * fo.z * pB * pV), 2.0f * fo.z * pB * pS,
+                             -fo.w * pB * il * il);
+        }
+        point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
     }
 
     // ---- FP64 reduction of the constant adjoints: waves (all constants
@@ -772,6 +862,8 @@ static int valid_desc(const gk_grid_desc* d) {
     if (d->n_discs < 0 || d->n_discs > 2) return fail(GK_EINVAL, "n_discs must be 0, 1 or 2");
     if (d->halo < GK_HALO_NONE || d->halo > GK_HALO_NFW) return fail(GK_EINVAL, "unknown halo kind %d", d->halo);
     if (d->halo == GK_HALO_NFW && !(d->hubble_h > 0.0)) return fail(GK_EINVAL, "hubble_h must be > 0");
+    if (d->psf_mode != GK_PSF_MAPS && d->psf_mode != GK_PSF_LUMINOSITY)
+        return fail(GK_EINVAL, "unknown psf_mode %d", d->psf_mode);
     if (d->bulge == GK_BULGE_NONE && d->n_discs == 0)
         return fail(GK_EINVAL, "the model needs at least one luminous component");
     return GK_OK;
@@ -857,9 +949,12 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int 
     const int nfrm = nfr_max(band_h, s, pad);
     int gs = steps > 0 ? steps : std::max(1, (10 + s / 2) / s);
     gs = std::min({gs, GSUB_CAP, std::max(1, RS_CAP / s)});
-    while (gs > 1 && make_layout(gs * s, c.xw, nfrm, band_h).total_bytes > (steps > 0 ? 64 : 40) * 1024) --gs;
+    const int lw = g->geo.lw;
+    while (gs > 1 && make_layout(gs * s, c.xw, nfrm, band_h, lw ? 8 * gs * band_w : 0).total_bytes >
+                         (steps > 0 ? 64 : 40) * 1024)
+        --gs;
     c.gsub = gs;
-    c.lds = make_layout(gs * s, c.xw, nfrm, band_h).total_bytes;
+    c.lds = make_layout(gs * s, c.xw, nfrm, band_h, lw ? 8 * gs * band_w : 0).total_bytes;
     if (c.lds > 64 * 1024) return fail(GK_EINVAL, "launch shape needs %d bytes of LDS (> 64 KiB)", c.lds);
     return GK_OK;
 }
@@ -1082,6 +1177,7 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
     g->geo.bulge = desc->bulge;
     g->geo.ndisc = desc->n_discs;
     g->geo.halo = desc->halo;
+    g->geo.lw = desc->psf_mode == GK_PSF_LUMINOSITY ? 1 : 0;
     g->P = 4 + 3 * (desc->bulge != 0) + 4 * desc->n_discs + 2 * (desc->halo != 0);
     // 1-D Gaussian factors (FP32) and the stencil half-widths
     std::vector<float> gw(pad + 1);

@@ -48,6 +48,7 @@ struct GridGeom {
     double pk;
     double rho_crit;     // Msun / kpc^3
     int bulge, ndisc, halo;
+    int lw;              // 1: luminosity-weighted PSF moments instead of averaged maps
 };
 
 __device__ __forceinline__ bool gk_finite(double x) { return x == x && fabs(x) <= 1.7e308; }

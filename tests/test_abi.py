@@ -38,7 +38,8 @@ def test_argument_errors_without_device():
     assert lib.create_grid(None, 4, ctypes.byref(h)) == gk.GK_EINVAL
     assert "NULL" in gk.last_error()
     bad = [dict(nx=0), dict(supersample=2), dict(supersample=0), dict(psf_sigma_px=-1.0),
-           dict(n_discs=3), dict(halo=5), dict(bulge=0, n_discs=0), dict(pixel_kpc=0.0), dict(bulge=3)]
+           dict(n_discs=3), dict(halo=5), dict(bulge=0, n_discs=0), dict(pixel_kpc=0.0), dict(bulge=3),
+           dict(psf_mode=2), dict(psf_mode=-1)]
     for over in bad:
         d = dict(nx=10, ny=10, pixel_kpc=0.1, supersample=3, psf_sigma_px=1.0, bulge=1,
                  n_discs=1, halo=2, hubble_h=0.7)

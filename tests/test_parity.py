@@ -43,9 +43,17 @@ def oracle_maps(spec, th):
     return np.stack([F[0], F[1], F[2], 1.0 / F[3]])
 
 
-def check_maps(got, ref, tag):
+def check_maps(got, ref, tag, lw=False):
     got = np.asarray(got, dtype=np.float64)
     for m in (0, 2, 3):
+        if lw and m == 2:
+            # sigma^2 = F2/F0 - v^2 from FP32 moment sums of relative error
+            # ~MAP_EPS: |d sigma| <= MAP_EPS (sigma^2 + v^2) / (2 sigma)
+            sg, v = ref[2], ref[1]
+            bound = MAP_RTOL * sg + MAP_EPS * (sg * sg + v * v) / (2.0 * np.maximum(sg, 1e-30))
+            bad = np.abs(got[2] - sg) > bound
+            assert not bad.any(), f"{tag} LW dispersion: {np.abs(got[2] - sg)[bad][:4]} > {bound[bad][:4]}"
+            continue
         rel = np.max(np.abs(got[m] / ref[m] - 1.0))
         assert rel < MAP_RTOL, f"{tag} map {m}: rel err {rel:.3e}"
     vmax = np.max(np.abs(ref[1]))
@@ -77,6 +85,13 @@ CASES = {
     "jaffe_2d_nfw": (W.GridSpec(33, 29, 0.15, 3, 1.06, W.BULGE_JAFFE, 2, W.HALO_NFW), (14.0, 12.0), 6),
     "jaffe_only_s5": (W.GridSpec(19, 17, 0.25, 5, 0.7, W.BULGE_JAFFE, 0, W.HALO_NONE), None, 4),
     "jaffe_1d_hq_s1": (W.GridSpec(30, 26, 0.3, 1, 1.3, W.BULGE_JAFFE, 1, W.HALO_HERNQUIST), None, 6),
+    # luminosity-weighted PSF moments instead of averaged maps
+    "lw_2d_nfw": (W.GridSpec(33, 29, 0.15, 3, 1.06, 1, 2, W.HALO_NFW, psf_mode=W.PSF_LUMINOSITY),
+                  (14.0, 12.0), 6),
+    "lw_jaffe_1d_hq_s1": (W.GridSpec(30, 26, 0.3, 1, 1.3, W.BULGE_JAFFE, 1, W.HALO_HERNQUIST,
+                                     psf_mode=W.PSF_LUMINOSITY), None, 4),
+    "lw_nobulge_s5": (W.GridSpec(19, 21, 0.25, 5, 0.8, 0, 2, W.HALO_NONE, psf_mode=W.PSF_LUMINOSITY),
+                      None, 4),
 }
 
 
@@ -105,7 +120,7 @@ def test_maps_and_loglike_match_oracle(gk, name):
     worst_map = 0.0
     for k, t in enumerate(thetas):
         ref = oracle_maps(spec, t)
-        e, ev = check_maps(maps[k], ref, f"{name}[{k}]")
+        e, ev = check_maps(maps[k], ref, f"{name}[{k}]", lw=spec.psf_mode == W.PSF_LUMINOSITY)
         worst_map = max(worst_map, e, ev)
         lo = M.loglike(spec, data, err, t)
         tol = LOGL_ATOL if k == 0 else logl_bound(spec, data, err, t)
@@ -116,9 +131,10 @@ def test_maps_and_loglike_match_oracle(gk, name):
     grid.close()
 
 
-def test_band_shapes_do_not_change_results(gk):
-    spec, data, err, thetas = make_case("ragged_s3_2d_hq")
-    say("[parity] band shapes on ragged_s3_2d_hq")
+@pytest.mark.parametrize("name", ["ragged_s3_2d_hq", "lw_2d_nfw"])
+def test_band_shapes_do_not_change_results(gk, name):
+    spec, data, err, thetas = make_case(name)
+    say(f"[parity] band shapes on {name}")
     th = torch.tensor(thetas, dtype=torch.float64, device="cuda")
     grid = gk.Grid(spec, max_batch=64)
     grid.set_data(data, err)
@@ -126,12 +142,33 @@ def test_band_shapes_do_not_change_results(gk):
     ref_maps = grid.maps(th).cpu()
     ref_l = grid.loglike(th).cpu()
     for bh, bw in [(1, 1), (5, 7), (8, 37), (23, 4), (3, 16)]:
-        grid.set_launch_shape(1, bh, bw)
-        mp = grid.maps(th).cpu()
-        ll = grid.loglike(th).cpu()
-        assert torch.equal(mp, ref_maps), (bh, bw)
-        np.testing.assert_allclose(ll.numpy(), ref_l.numpy(), rtol=1e-12, atol=1e-9)
+        for steps in (0, 1, 2):            # pixel rows per model phase (0: default)
+            grid.set_launch_shape(1, bh, bw, steps)
+            mp = grid.maps(th).cpu()
+            ll = grid.loglike(th).cpu()
+            assert torch.equal(mp, ref_maps), (bh, bw, steps)
+            np.testing.assert_allclose(ll.numpy(), ref_l.numpy(), rtol=1e-12, atol=1e-9)
     grid.close()
+
+
+def test_luminosity_weighting_without_psf_equals_plain_maps(gk):
+    """With no PSF every pixel is one lattice point, so the moment ratios give
+    back the point model: both modes agree up to FP32 rounding."""
+    base = W.GridSpec(21, 20, 0.2, 3, 0.0, 1, 1, W.HALO_NFW)
+    lw = W.GridSpec(21, 20, 0.2, 3, 0.0, 1, 1, W.HALO_NFW, psf_mode=W.PSF_LUMINOSITY)
+    rng = np.random.default_rng(zlib.crc32(b"lw-nopsf"))
+    th = torch.tensor(W.draw_thetas(base, 6, rng), dtype=torch.float64, device="cuda")
+    ga, gb = gk.Grid(base, max_batch=8), gk.Grid(lw, max_batch=8)
+    a, b = ga.maps(th).cpu().numpy(), gb.maps(th).cpu().numpy()
+    for m in (0, 3):
+        np.testing.assert_allclose(b[:, m], a[:, m], rtol=1e-6)
+    vmax = np.abs(a[:, 1]).max()
+    assert np.abs(b[:, 1] - a[:, 1]).max() <= 1e-6 * vmax
+    # sigma through sqrt(F2/F0 - v^2): absolute error ~ eps (sigma^2 + v^2) / sigma
+    bound = 1e-6 * a[:, 2] + 1e-6 * (a[:, 2] ** 2 + a[:, 1] ** 2) / a[:, 2]
+    assert (np.abs(b[:, 2] - a[:, 2]) <= bound).all()
+    ga.close()
+    gb.close()
 
 
 def test_determinism_and_edge_cases(gk):
@@ -198,7 +235,8 @@ def check_grad(got, ref, tag):
 @pytest.mark.parametrize("name,n", [("tiny", 4), ("ragged_s3_2d_hq", 3), ("nobulge_1d", 3),
                                     ("nobulge_2d_nohalo", 3), ("bulge_only_s5", 3), ("no_psf", 3),
                                     ("realistic", 2), ("jaffe_2d_nfw", 3), ("jaffe_only_s5", 2),
-                                    ("jaffe_1d_hq_s1", 2)])
+                                    ("jaffe_1d_hq_s1", 2), ("lw_2d_nfw", 3), ("lw_jaffe_1d_hq_s1", 2),
+                                    ("lw_nobulge_s5", 2)])
 def test_gradient_matches_oracle(gk, name, n):
     spec, data, err, thetas = make_case(name)
     thetas = thetas[:n]
