@@ -100,6 +100,12 @@ def rho_crit(hubble_h: float) -> float:
 # ---------------------------------------------------------------------------
 # the model at arbitrary sky positions
 # ---------------------------------------------------------------------------
+def frame_scale(spec: GridSpec) -> float:
+    """This grid's pixels per pixel of the frame the centre parameters use."""
+    f = getattr(spec, "frame_px_kpc", 0.0)
+    return f / spec.pixel_kpc if f > 0.0 else 1.0
+
+
 def point_model(spec: GridSpec, theta, x_px, y_px):
     """(B, v_los, sigma_los, <L/M>) at sky positions given in pixel coordinates.
 
@@ -112,9 +118,10 @@ def point_model(spec: GridSpec, theta, x_px, y_px):
     x_px = np.asarray(x_px, dtype=np.float64)
     y_px = np.asarray(y_px, dtype=np.float64)
 
-    # 1. frame
-    xc = 0.5 * (spec.nx - 1) + p["x0"]
-    yc = 0.5 * (spec.ny - 1) + p["y0"]
+    # 1. frame; (x0, y0) may be given in a shared frame of another pixel size
+    fs = frame_scale(spec)
+    xc = 0.5 * (spec.nx - 1) + getattr(spec, "frame_dx", 0.0) + fs * p["x0"]
+    yc = 0.5 * (spec.ny - 1) + getattr(spec, "frame_dy", 0.0) + fs * p["y0"]
     dx = (x_px - xc) * spec.pixel_kpc
     dy = (y_px - yc) * spec.pixel_kpc
     pa = p["PA"] * (math.pi / 180.0)
@@ -367,6 +374,20 @@ def grad_central_fd(spec: GridSpec, data, err, theta, rel: float = 1e-6) -> np.n
         tm[k] -= hk
         g[k] = (loglike(spec, data, err, tp) - loglike(spec, data, err, tm)) / (tp[k] - tm[k])
     return g
+
+
+def loglike_joint(specs, datas, errs, theta):
+    """Several observations of one galaxy, each map set on its own pixel grid
+    (the method takes observables mapped on different numbers of pixels, as
+    the comparison with DYNAMITE in Sec. 3.2 points out): the
+    Gaussian terms of the likelihood simply add over the grids, each grid
+    contributing the maps it carries (a map it does not carry has zero
+    errors, hence no valid pixels)."""
+    return sum(loglike(sp, d, e, theta) for sp, d, e in zip(specs, datas, errs))
+
+
+def grad_joint_complex_step(specs, datas, errs, theta) -> np.ndarray:
+    return sum(grad_complex_step(sp, d, e, theta) for sp, d, e in zip(specs, datas, errs))
 
 
 def loglike_batch(spec: GridSpec, data, err, thetas) -> np.ndarray:

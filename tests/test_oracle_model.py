@@ -335,3 +335,60 @@ def test_lw_dispersion_includes_unresolved_rotation():
     th = theta_for(spec, k1=0.9, k2=0.9)
     F0, F1 = M.psf_maps(spec, th), M.psf_maps(_lw(spec), th)
     assert np.median(F1[2] - F0[2]) > 0
+
+
+# --- per-map pixelisation: a shared frame for the centre parameters --------
+def test_frame_of_own_pixel_size_changes_nothing():
+    spec = spec_small()
+    same = spec_small(frame_px_kpc=spec.pixel_kpc)
+    th = theta_for(spec)
+    assert M.frame_scale(same) == 1.0
+    np.testing.assert_array_equal(M.psf_maps(same, th), M.psf_maps(spec, th))
+
+
+def test_frame_scale_samples_the_same_sky_on_a_finer_grid():
+    """Without PSF and supersampling a map is the model at the pixel centres:
+    a grid of half the pixel size, its centre parameters given in the coarse
+    grid's pixels, holds the coarse map at every second pixel."""
+    coarse = spec_small(nx=15, ny=11, pixel_kpc=0.2, supersample=1, psf_sigma_px=0.0)
+    fine = spec_small(nx=29, ny=21, pixel_kpc=0.1, supersample=1, psf_sigma_px=0.0, frame_px_kpc=0.2)
+    th = theta_for(coarse, x0=0.37, y0=-0.61)
+    assert M.frame_scale(fine) == 2.0
+    a = M.psf_maps(coarse, th)
+    b = M.psf_maps(fine, th)[:, ::2, ::2]
+    for m in (0, 2, 3):
+        np.testing.assert_allclose(b[m], a[m], rtol=1e-12)
+    np.testing.assert_allclose(b[1], a[1], atol=1e-10 * np.abs(a[1]).max())
+
+
+def test_frame_offset_cuts_a_window_out_of_a_larger_grid():
+    """A small grid that covers columns 7..17 and rows 2..10 of a larger grid
+    of the same pixels, PSF and lattice holds the larger grid's maps there,
+    PSF included: its frame centre (the larger grid's centre) sits at
+    (10 - 7, 8 - 2) of its own pixels, i.e. (-2, +2) from its own centre."""
+    big = spec_small(nx=21, ny=17)
+    win = spec_small(nx=11, ny=9, frame_dx=-2.0, frame_dy=2.0)
+    th = theta_for(big)
+    a = M.psf_maps(big, th)[:, 2:11, 7:18]
+    b = M.psf_maps(win, th)
+    for m in (0, 2, 3):
+        np.testing.assert_allclose(b[m], a[m], rtol=1e-12)
+    np.testing.assert_allclose(b[1], a[1], atol=1e-10 * np.abs(a[1]).max())
+
+
+def test_joint_likelihood_of_maps_split_over_grids_equals_one_grid():
+    """The four Gaussian terms are independent: one grid carrying B and
+    another carrying v, sigma and M/L (zero errors elsewhere) give the
+    likelihood of one grid carrying all four."""
+    spec = spec_small()
+    th = theta_for(spec)
+    rng = np.random.default_rng(11)
+    data, err = M.synthetic_data(spec, th, np.ones((spec.ny, spec.nx), bool), rng)
+    ea, eb = err.copy(), err.copy()
+    ea[1:] = 0.0
+    eb[0] = 0.0
+    t2 = theta_for(spec, Rd1=1.5, incl=48.0)
+    one = M.loglike(spec, data, err, t2)
+    two = M.loglike_joint([spec, spec], [data, data], [ea, eb], t2)
+    assert two == pytest.approx(one, rel=1e-13)
+    assert M.loglike(spec, data, ea, t2) != pytest.approx(one, rel=1e-3)

@@ -22,7 +22,8 @@ each disc j           log10 Mdj [Msun], Rdj [kpc], (M/L)dj, kj
 halo (if present)     log10 Mh [Msun], then c (NFW) or Rh [kpc] (Hernquist)
 ====================  =====================================================
 
-The galaxy centre sits at the grid centre plus (x0, y0) pixels.  x is the
+The galaxy centre sits at the grid centre plus (x0, y0) pixels (pixels of a
+shared frame, possibly offset, when ``GridSpec.frame_px_kpc`` is set).  x is the
 column index (fastest varying), y the row index, maps are stored [ny][nx].
 """
 from __future__ import annotations
@@ -59,6 +60,13 @@ class GridSpec:
     halo: int = HALO_NFW
     hubble_h: float = 0.7
     psf_mode: int = 0         # PSF_MAPS (each map averaged) or PSF_LUMINOSITY (moments)
+    # shared frame of the centre parameters when several grids (one per
+    # pixelisation) see the same galaxy: x0, y0 are in pixels of size
+    # frame_px_kpc (0: this grid's own pixels), and the frame's centre sits
+    # frame_dx, frame_dy pixels of this grid from this grid's centre
+    frame_px_kpc: float = 0.0
+    frame_dx: float = 0.0
+    frame_dy: float = 0.0
 
     @property
     def n_params(self) -> int:
