@@ -74,6 +74,13 @@ typedef struct {
                            /* (Sec. 3.1); GK_PSF_LUMINOSITY: the PSF averages   */
                            /* B, B v, B (sigma^2 + v^2) and the mass density,   */
                            /* and v, sigma, M/L follow from their ratios        */
+    /* Observations of one galaxy on several pixelisations (one grid each,     */
+    /* Sec. 3.2: the maps may come with different numbers of pixels) share the */
+    /* centre parameters x0, y0 through a common frame:                        */
+    double frame_px_kpc;   /* pixel size of the frame x0, y0 are measured in;  */
+                           /* 0 (or this grid's pixel_kpc): its own pixels     */
+    double frame_dx;       /* the frame's centre, in this grid's pixels, from  */
+    double frame_dy;       /* this grid's centre (0, 0 when they coincide)     */
 } gk_grid_desc;
 
 /* Create a grid handle on the current HIP device.  Allocates every device
@@ -132,6 +139,20 @@ int eval_maps(gk_grid_t grid, const double* theta, int B, int stride, float* map
  * captured once in a HIP graph and replayed. */
 int hmc_leapfrog(gk_grid_t grid, double* theta, double* momentum, const double* inv_mass, double eps,
                  int n_steps, int B, int stride, double* logL, double* grad, void* hip_stream);
+
+/* Joint log-likelihood of ONE galaxy observed on several pixelisations
+ * (Sec. 3.2: the observables may be mapped with different numbers of pixels;
+ * the Gaussian terms of Sec. 2.5.1 add over the grids).  grids: host array of
+ * n_grids >= 1 distinct handles with data, on the current device, all with
+ * the same component set (the same parameter vector; their descriptors' frame
+ * fields place the shared centre).  A grid contributes the maps it carries:
+ * give zero errors in set_data for the maps it does not.  theta: device
+ * float64 [B][stride]; logL[b] = sum over grids of each grid's logL; grad
+ * (may be NULL) likewise summed.  Grid 0's launch stores, the others add, in
+ * grid order on the stream, so repeated calls give identical results.  Uses
+ * the grids' workspaces; allocates nothing. */
+int loglike_joint(const gk_grid_t* grids, int n_grids, const double* theta, int B, int stride,
+                  double* logL, double* grad, void* hip_stream);
 
 /* Log-likelihoods of many galaxies in ONE persistent launch (the batched
  * form of the paper's per-galaxy likelihood, Sec. 2.5.1, over a catalogue).

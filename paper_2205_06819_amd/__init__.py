@@ -28,7 +28,7 @@ GK_HALO_NONE, GK_HALO_HERNQUIST, GK_HALO_NFW = 0, 1, 2
 GK_PSF_MAPS, GK_PSF_LUMINOSITY = 0, 1
 
 EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",
-           "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "ml_from_colour",
+           "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "loglike_joint", "ml_from_colour",
            "brightness_errors", "last_error")
 
 
@@ -42,7 +42,9 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("pixel_kpc", ctypes.c_double),
                 ("supersample", ctypes.c_int), ("psf_sigma_px", ctypes.c_double),
                 ("bulge", ctypes.c_int), ("n_discs", ctypes.c_int), ("halo", ctypes.c_int),
-                ("hubble_h", ctypes.c_double), ("psf_mode", ctypes.c_int)]
+                ("hubble_h", ctypes.c_double), ("psf_mode", ctypes.c_int),
+                ("frame_px_kpc", ctypes.c_double), ("frame_dx", ctypes.c_double),
+                ("frame_dy", ctypes.c_double)]
 
 
 def _load() -> ctypes.CDLL:
@@ -63,6 +65,7 @@ def _load() -> ctypes.CDLL:
     lib.set_launch_shape.argtypes = [vp, i, i, i, i]
     lib.hmc_leapfrog.argtypes = [vp, vp, vp, vp, d, i, i, i, vp, vp, vp]
     lib.loglike_multi.argtypes = [vp, i, vp, vp, i, vp, vp, vp]
+    lib.loglike_joint.argtypes = [vp, i, vp, i, i, vp, vp, vp]
     lib.ml_from_colour.argtypes = [vp, vp, vp, vp, i, d, d, d, vp, vp, vp]
     lib.brightness_errors.argtypes = [vp, i, d, d, vp, vp]
     lib.last_error.restype = ctypes.c_char_p
@@ -95,7 +98,9 @@ def make_desc(spec) -> GridDesc:
     """GridDesc from any object with the descriptor's attribute names."""
     return GridDesc(int(spec.nx), int(spec.ny), float(spec.pixel_kpc), int(spec.supersample),
                     float(spec.psf_sigma_px), int(spec.bulge), int(spec.n_discs), int(spec.halo),
-                    float(getattr(spec, "hubble_h", 0.7)), int(getattr(spec, "psf_mode", 0)))
+                    float(getattr(spec, "hubble_h", 0.7)), int(getattr(spec, "psf_mode", 0)),
+                    float(getattr(spec, "frame_px_kpc", 0.0)), float(getattr(spec, "frame_dx", 0.0)),
+                    float(getattr(spec, "frame_dy", 0.0)))
 
 
 # --- C-ABI names -------------------------------------------------------------
@@ -211,6 +216,27 @@ def loglike_multi(handles, theta: torch.Tensor, theta_offset, out: Optional[torc
         raise ValueError("grad must be float64 with theta's row stride")
     _check(_lib.loglike_multi(hs, n, theta.data_ptr(), offs.ctypes.data, theta.stride(0), out.data_ptr(),
                               _ptr(grad), _stream(stream)))
+    return out
+
+
+def loglike_joint(handles, theta: torch.Tensor, out: Optional[torch.Tensor] = None,
+                  grad: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Joint log-likelihood of one galaxy observed on several grids (one per
+    pixelisation, sharing the parameter vector): logL[b] = sum over the
+    grids.  With grad given (float64, theta's shape) the summed gradient is
+    written too."""
+    n = len(handles)
+    if not (theta.is_cuda and theta.dtype == torch.float64 and theta.dim() == 2 and theta.stride(1) == 1):
+        raise ValueError("theta must be a contiguous-row float64 CUDA tensor [B, stride]")
+    hs = (ctypes.c_void_p * max(1, n))(*[ctypes.c_void_p(h) for h in handles])
+    B = theta.shape[0]
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=theta.device)
+    if grad is not None and (grad.stride(0) != theta.stride(0) or grad.stride(1) != 1 or grad.dtype != torch.float64
+                             or grad.shape[0] < B):
+        raise ValueError("grad must be float64 [B, stride] with theta's row stride")
+    _check(_lib.loglike_joint(hs, n, theta.data_ptr(), B, theta.stride(0), out.data_ptr(), _ptr(grad),
+                              _stream(stream)))
     return out
 
 

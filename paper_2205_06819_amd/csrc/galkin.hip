@@ -61,6 +61,7 @@ struct FwdArgs {
     float* fbar;            // MODE_FBAR output [B][4][ny][nx]: d logL / d F
     double* partials;       // [B][pstride]
     unsigned* counters;     // [B]
+    int accum;              // 1: add the log-likelihood to logL[b] instead of storing it
 };
 
 constexpr int DMAX = 10;        // largest lag D = floor(2 pad / s) supported
@@ -430,6 +431,10 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
                         gbar = o2 * hs2 * ds2_2;
                     else
                         gbar = o3 * i0;
+                    // a pixel with no valid map (outside every map's column span the
+                    // lattice is not evaluated, F0 may be 0) has a zero adjoint
+                    const bool used = (o0 != 0.0f) | (o1 != 0.0f) | (o2 != 0.0f) | (o3 != 0.0f);
+                    gbar = used ? gbar : 0.0f;
                     const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
                     if (pact) a.fbar[mapoff + pix] = gbar;
                 }
@@ -448,7 +453,8 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
         double t = 0.0;
         for (int w = 0; w < (BS + 63) / 64; ++w) t += s_red[w];
         if (a.nbands == 1) {
-            a.logL[b] = -0.5 * (t + *a.logdet);
+            const double v = -0.5 * (t + *a.logdet);
+            a.logL[b] = a.accum ? a.logL[b] + v : v;
         } else {
             a.partials[(size_t)b * a.pstride + band] = t;
             const unsigned ticket = __hip_atomic_fetch_add(a.counters + b, 1u, __ATOMIC_ACQ_REL,
@@ -458,7 +464,8 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
                 for (int k = 0; k < a.nbands; ++k)
                     sum += __hip_atomic_load(a.partials + (size_t)b * a.pstride + k, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
-                a.logL[b] = -0.5 * (sum + *a.logdet);
+                const double v = -0.5 * (sum + *a.logdet);
+                a.logL[b] = a.accum ? a.logL[b] + v : v;
                 __hip_atomic_store(a.counters + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -531,6 +538,7 @@ struct AdjArgs {
     double* gpart;          // [B][nbands][NCONST] per-band constant adjoints
     unsigned* counters;     // [B], zero on entry, reset by the last band
     double* grad;           // [B][stride]
+    int accum;              // 1: add the gradient to grad[b] instead of storing it
 };
 
 __host__ __device__ inline int adj_lds_bytes(int band_h, int band_w, int s, int pad) {
@@ -542,9 +550,10 @@ __host__ __device__ inline int adj_lds_bytes(int band_h, int band_w, int s, int 
 __device__ inline int floor_div(int n, int d) { return n >= 0 ? n / d : -((-n + d - 1) / d); }
 
 // Chain rule from the adjoints of the FP32 constants of make_tc to the
-// parameters (FP64), then writes the gradient row (zeros past P).
+// parameters (FP64), then writes the gradient row (zeros past P), or adds it
+// to the row (accum; the padding columns are left alone).
 __device__ inline void chain_rule(const double* th, const GridGeom& g, const double* cb, double* out,
-                                  int stride) {
+                                  int stride, int accum) {
     const double d2r = PI / 180.0, LN10 = 2.302585092994046;
     double gr[32];
     for (int k = 0; k < 32; ++k) gr[k] = 0.0;
@@ -553,8 +562,8 @@ __device__ inline void chain_rule(const double* th, const GridGeom& g, const dou
     sincos(pa, &spa, &cpa);
     sincos(inc, &si, &ci);
     const double pks = g.pk / g.s;
-    gr[0] = cb[C_UF] * g.s;
-    gr[1] = cb[C_VF] * g.s;
+    gr[0] = cb[C_UF] * g.s * g.fscale;
+    gr[1] = cb[C_VF] * g.s * g.fscale;
     gr[2] = (cb[C_CA] * (-pks * spa) + cb[C_SA] * (pks * cpa)) * d2r;
     gr[3] = cb[C_SEC2I] * 2.0 * si / (ci * ci * ci) * d2r;
     int k = 4;
@@ -599,7 +608,10 @@ __device__ inline void chain_rule(const double* th, const GridGeom& g, const dou
         gr[k + 1] = cb[C_H0];
         k += 2;
     }
-    for (int q = 0; q < stride; ++q) out[q] = q < k ? gr[q] : 0.0;
+    if (accum)
+        for (int q = 0; q < k; ++q) out[q] += gr[q];
+    else
+        for (int q = 0; q < stride; ++q) out[q] = q < k ? gr[q] : 0.0;
 }
 
 template <int BULGE, int NDISC, int HALO>
@@ -629,7 +641,7 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
     const double* th = a.theta + (size_t)b * a.stride;
     const TC tc = uniform_tc(make_tc(th, G));
     if (!tc.valid) {
-        if (band == 0)
+        if (band == 0 && !a.accum)
             for (int q = tid; q < a.stride; q += BS) a.grad[(size_t)b * a.stride + q] = 0.0;
         return;
     }
@@ -767,7 +779,7 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
                 for (int k = 0; k < NCONST; ++k)
                     cb[k] += __hip_atomic_load(a.gpart + ((size_t)b * a.nbands + bnd) * NCONST + k,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            chain_rule(th, G, cb, a.grad + (size_t)b * a.stride, a.stride);
+            chain_rule(th, G, cb, a.grad + (size_t)b * a.stride, a.stride, a.accum);
             if (a.nbands > 1) __hip_atomic_store(a.counters + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -864,6 +876,9 @@ static int valid_desc(const gk_grid_desc* d) {
     if (d->halo == GK_HALO_NFW && !(d->hubble_h > 0.0)) return fail(GK_EINVAL, "hubble_h must be > 0");
     if (d->psf_mode != GK_PSF_MAPS && d->psf_mode != GK_PSF_LUMINOSITY)
         return fail(GK_EINVAL, "unknown psf_mode %d", d->psf_mode);
+    if (!(d->frame_px_kpc >= 0.0) || !std::isfinite(d->frame_px_kpc) || !std::isfinite(d->frame_dx) ||
+        !std::isfinite(d->frame_dy))
+        return fail(GK_EINVAL, "frame_px_kpc must be finite and >= 0, frame_dx and frame_dy finite");
     if (d->bulge == GK_BULGE_NONE && d->n_discs == 0)
         return fail(GK_EINVAL, "the model needs at least one luminous component");
     return GK_OK;
@@ -1027,6 +1042,7 @@ static void fill_args(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, const do
     a.fbar = nullptr;
     a.partials = g->d_partials;
     a.counters = g->d_counters;
+    a.accum = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1178,6 +1194,9 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
     g->geo.ndisc = desc->n_discs;
     g->geo.halo = desc->halo;
     g->geo.lw = desc->psf_mode == GK_PSF_LUMINOSITY ? 1 : 0;
+    g->geo.fscale = desc->frame_px_kpc > 0.0 ? desc->frame_px_kpc / desc->pixel_kpc : 1.0;
+    g->geo.fdx = desc->frame_dx;
+    g->geo.fdy = desc->frame_dy;
     g->P = 4 + 3 * (desc->bulge != 0) + 4 * desc->n_discs + 2 * (desc->halo != 0);
     // 1-D Gaussian factors (FP32) and the stencil half-widths
     std::vector<float> gw(pad + 1);
@@ -1345,22 +1364,32 @@ int set_data(gk_grid_t g, const float* value, const float* err, int on_device, v
     return GK_OK;
 }
 
+// log-likelihood launch of one grid (arguments checked by the caller)
+static int run_loglike(gk_grid* g, const double* theta, int B, int stride, double* logL, int accum,
+                       hipStream_t st) {
+    int bh, bw, steps;
+    choose_rule(g, B, bh, bw, steps);
+    LaunchCfg c;
+    int rc = make_cfg(g, bh, bw, c, 0, steps);
+    if (rc) return rc;
+    FwdArgs a;
+    fill_args(g, c, a, theta, stride);
+    a.logL = logL;
+    a.accum = accum;
+    hipError_t e = launch_fwd<MODE_LOGL>(g, c, a, B, st);
+    if (e != hipSuccess) return fail(GK_EHIP, "forward launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
+}
+
+static int run_grad(gk_grid* g, const double* theta, int B, int stride, double* logL, double* grad, int accum,
+                    hipStream_t st);
+
 int loglike_batch(gk_grid_t g, const double* theta, int B, int stride, double* logL, void* stream) {
     int rc = check_call(g, theta, B, stride, logL);
     if (rc) return rc;
     if (!g->has_data) return fail(GK_ESTATE, "loglike_batch before set_data");
     if (B == 0) return GK_OK;
-    int bh, bw, steps;
-    choose_rule(g, B, bh, bw, steps);
-    LaunchCfg c;
-    rc = make_cfg(g, bh, bw, c, 0, steps);
-    if (rc) return rc;
-    FwdArgs a;
-    fill_args(g, c, a, theta, stride);
-    a.logL = logL;
-    hipError_t e = launch_fwd<MODE_LOGL>(g, c, a, B, (hipStream_t)stream);
-    if (e != hipSuccess) return fail(GK_EHIP, "forward launch failed: %s", hipGetErrorString(e));
-    return GK_OK;
+    return run_loglike(g, theta, B, stride, logL, 0, (hipStream_t)stream);
 }
 
 int eval_maps(gk_grid_t g, const double* theta, int B, int stride, float* maps, void* stream) {
@@ -1387,17 +1416,22 @@ int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, doub
     if (B > 0 && !grad) return fail(GK_EINVAL, "NULL grad");
     if (!g->has_data) return fail(GK_ESTATE, "loglike_grad_batch before set_data");
     if (B == 0) return GK_OK;
-    hipStream_t st = (hipStream_t)stream;
+    return run_grad(g, theta, B, stride, logL, grad, 0, (hipStream_t)stream);
+}
+
+static int run_grad(gk_grid* g, const double* theta, int B, int stride, double* logL, double* grad, int accum,
+                    hipStream_t st) {
     // pass 1: log-likelihood and d logL / d F at every pixel
     int bh, bw, steps;
     choose_rule(g, B, bh, bw, steps);
     LaunchCfg c;
-    rc = make_cfg(g, bh, bw, c, 0, steps);
+    int rc = make_cfg(g, bh, bw, c, 0, steps);
     if (rc) return rc;
     FwdArgs fa;
     fill_args(g, c, fa, theta, stride);
     fa.logL = logL;
     fa.fbar = g->d_fbar;
+    fa.accum = accum;
     hipError_t e = launch_fwd<MODE_FBAR>(g, c, fa, B, st);
     if (e != hipSuccess) return fail(GK_EHIP, "forward (adjoint seed) launch failed: %s", hipGetErrorString(e));
     // pass 2: adjoint of the PSF and of the model, chain rule to theta
@@ -1418,6 +1452,7 @@ int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, doub
     aa.gpart = g->d_gpart;
     aa.counters = g->d_counters;
     aa.grad = grad;
+    aa.accum = accum;
     const int lds = adj_lds_bytes(aa.band_h, aa.band_w, g->geo.s, g->geo.pad);
     const dim3 grid2((unsigned)(B * aa.nbands)), block2(256);
     const int bulge = g->d.bulge, nd = g->d.n_discs, halo = g->d.halo;
@@ -1439,6 +1474,35 @@ int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, doub
     e = hipGetLastError();
     if (!launched || e != hipSuccess)
         return fail(GK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
+}
+
+int loglike_joint(const gk_grid_t* grids, int n_grids, const double* theta, int B, int stride, double* logL,
+                  double* grad, void* stream) {
+    if (n_grids < 1 || !grids) return fail(GK_EINVAL, "loglike_joint needs n_grids >= 1 and a grid list");
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(GK_EHIP, "hipGetDevice failed");
+    for (int i = 0; i < n_grids; ++i) {
+        const gk_grid* g = grids[i];
+        int rc = check_call(g, theta, B, stride, logL);
+        if (rc) return rc;
+        if (!g->has_data) return fail(GK_ESTATE, "grid %d has no data (set_data)", i);
+        if (g->device != device) return fail(GK_EINVAL, "grid %d lives on device %d, not %d", i, g->device, device);
+        const gk_grid* g0 = grids[0];
+        if (g->d.bulge != g0->d.bulge || g->d.n_discs != g0->d.n_discs || g->d.halo != g0->d.halo)
+            return fail(GK_EINVAL, "grid %d has another component set than grid 0", i);
+        for (int k = 0; k < i; ++k)
+            if (grids[k] == g) return fail(GK_EINVAL, "grid %d appears twice", i);
+    }
+    if (B == 0) return GK_OK;
+    hipStream_t st = (hipStream_t)stream;
+    // grid 0 stores, the others add, in stream order: the sum is taken in the
+    // same order on every call
+    for (int i = 0; i < n_grids; ++i) {
+        const int rc = grad ? run_grad(grids[i], theta, B, stride, logL, grad, i > 0, st)
+                            : run_loglike(grids[i], theta, B, stride, logL, i > 0, st);
+        if (rc) return rc;
+    }
     return GK_OK;
 }
 

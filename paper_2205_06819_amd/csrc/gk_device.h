@@ -49,6 +49,8 @@ struct GridGeom {
     double rho_crit;     // Msun / kpc^3
     int bulge, ndisc, halo;
     int lw;              // 1: luminosity-weighted PSF moments instead of averaged maps
+    double fscale;       // this grid's pixels per pixel of the centre parameters' frame
+    double fdx, fdy;     // that frame's centre, in this grid's pixels from its centre
 };
 
 __device__ __forceinline__ bool gk_finite(double x) { return x == x && fabs(x) <= 1.7e308; }
@@ -61,8 +63,8 @@ __device__ inline TC make_tc(const double* th, const GridGeom& g) {
     for (int k = 0; k < P; ++k) ok = ok && gk_finite(th[k]);
     const double x0 = th[0], y0 = th[1], pa = th[2] * (PI / 180.0), inc = th[3] * (PI / 180.0);
     ok = ok && th[3] > 0.0 && th[3] < 90.0;
-    const double Uc = (0.5 * (g.nx - 1) + x0) * g.s + g.hs + g.pad;
-    const double Vc = (0.5 * (g.ny - 1) + y0) * g.s + g.hs + g.pad;
+    const double Uc = (0.5 * (g.nx - 1) + g.fdx + g.fscale * x0) * g.s + g.hs + g.pad;
+    const double Vc = (0.5 * (g.ny - 1) + g.fdy + g.fscale * y0) * g.s + g.hs + g.pad;
     const double Uflo = floor(Uc), Vflo = floor(Vc);
     c.Ui = ok ? (int)Uflo : 0;
     c.Vi = ok ? (int)Vflo : 0;

@@ -39,7 +39,8 @@ def test_argument_errors_without_device():
     assert "NULL" in gk.last_error()
     bad = [dict(nx=0), dict(supersample=2), dict(supersample=0), dict(psf_sigma_px=-1.0),
            dict(n_discs=3), dict(halo=5), dict(bulge=0, n_discs=0), dict(pixel_kpc=0.0), dict(bulge=3),
-           dict(psf_mode=2), dict(psf_mode=-1)]
+           dict(psf_mode=2), dict(psf_mode=-1), dict(frame_px_kpc=-0.1), dict(frame_dx=float("nan")),
+           dict(frame_dy=float("inf"))]
     for over in bad:
         d = dict(nx=10, ny=10, pixel_kpc=0.1, supersample=3, psf_sigma_px=1.0, bulge=1,
                  n_discs=1, halo=2, hubble_h=0.7)
@@ -54,6 +55,8 @@ def test_argument_errors_without_device():
     assert lib.eval_maps(None, None, 1, 13, None, None) == gk.GK_EINVAL
     assert lib.set_data(None, None, None, 0, None) == gk.GK_EINVAL
     assert lib.destroy_grid(None) == gk.GK_EINVAL
+    assert lib.loglike_joint(None, 1, None, 1, 13, None, None, None) == gk.GK_EINVAL
+    assert lib.loglike_joint(None, 0, None, 1, 13, None, None, None) == gk.GK_EINVAL
     assert lib.set_launch_shape(None, 1, 1, 1, 0) == gk.GK_EINVAL
     assert lib.loglike_multi(None, -1, None, None, 13, None, None, None) == gk.GK_EINVAL
     assert lib.loglike_multi(None, 0, None, None, 13, None, None, None) == gk.GK_OK

@@ -80,7 +80,8 @@ def check_pixels(gk, grid, spec, thetas, rows, rng, n_pix=24):
 
 def check_grad(got, ref, tag):
     tol = GRAD_RTOL * np.abs(ref) + GRAD_NORM_TOL * np.linalg.norm(ref)
-    bad = np.abs(got - ref) > tol
+    assert np.isfinite(got).all() and np.isfinite(ref).all(), f"{tag}: non-finite gradient {got}"
+    bad = ~(np.abs(got - ref) <= tol)
     assert not bad.any(), f"{tag}: params {np.nonzero(bad)[0]}: gpu {got[bad]} oracle {ref[bad]}"
     return float(np.max(np.abs(got - ref) / (np.abs(ref) + np.linalg.norm(ref))))
 

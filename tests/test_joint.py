@@ -1,0 +1,153 @@
+"""GPU parity of observations on several pixelisations: grids whose centre
+parameters live in a shared frame (scale and offset), and the joint
+log-likelihood / gradient over several grids (loglike_joint) against the
+oracle's sum over grids."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import model as M
+
+pytestmark = pytest.mark.gpu
+
+LOGL_ATOL, MAP_EPS = 1e-3, 1e-5
+GRAD_RTOL, GRAD_NORM_TOL = 1e-3, 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_06819_amd as gk
+    return gk
+
+
+def logl_bound(spec, data, err, th):
+    """1e-3 plus the first-order effect of a relative map error MAP_EPS."""
+    F = M.psf_maps(spec, th)
+    F = np.stack([F[0], F[1], F[2], 1.0 / F[3]])
+    ok = M.valid_masks(data, err)
+    tot = 0.0
+    for m in range(4):
+        r = (F[m][ok[m]] - data[m][ok[m]]) / err[m][ok[m]]
+        tot += np.sum(np.abs(r) * np.abs(F[m][ok[m]]) / err[m][ok[m]])
+    return MAP_EPS * tot
+
+
+def check_grad(got, ref, tag):
+    tol = GRAD_RTOL * np.abs(ref) + GRAD_NORM_TOL * np.linalg.norm(ref)
+    assert np.isfinite(got).all() and np.isfinite(ref).all(), f"{tag}: non-finite gradient {got}"
+    bad = ~(np.abs(got - ref) <= tol)
+    assert not bad.any(), f"{tag}: params {np.nonzero(bad)[0]}: gpu {got[bad]} oracle {ref[bad]}"
+    return float(np.max(np.abs(got - ref) / (np.abs(ref) + np.linalg.norm(ref))))
+
+
+# photometry on a fine grid, kinematics on a coarse one, with the coarse
+# grid's pixels as the frame of the centre parameters
+PHOT = W.GridSpec(36, 32, 0.1, 1, 1.5, 1, 2, W.HALO_NFW, frame_px_kpc=0.2, frame_dx=0.7, frame_dy=-0.4)
+KIN = W.GridSpec(19, 17, 0.2, 3, 1.0, 1, 2, W.HALO_NFW)
+
+
+def two_grid_data(rng, n_rows):
+    truth = W.draw_thetas(KIN, 1, rng)[0]
+    truth[0], truth[1] = 0.4, -0.3
+    dp, ep = M.synthetic_data(PHOT, truth, np.ones((PHOT.ny, PHOT.nx), bool), rng)
+    dk, ek = M.synthetic_data(KIN, truth, W.elliptical_mask(KIN.nx, KIN.ny, 8.5, 7.5), rng)
+    ep[1:] = 0.0          # the photometric grid carries B only
+    ek[0] = 0.0           # the kinematic grid carries v, sigma and M/L
+    th = np.vstack([truth[None], W.draw_thetas(KIN, n_rows - 1, rng)])
+    th[1:, :2] = rng.uniform(-1.0, 1.0, (n_rows - 1, 2))
+    return (dp, ep), (dk, ek), th
+
+
+def test_joint_two_pixelisations_match_oracle(gk):
+    rng = np.random.default_rng(zlib.crc32(b"joint-two"))
+    (dp, ep), (dk, ek), th_np = two_grid_data(rng, 5)
+    say(f"[joint] photometry {PHOT.nx}x{PHOT.ny} @ {PHOT.pixel_kpc} kpc, kinematics "
+        f"{KIN.nx}x{KIN.ny} @ {KIN.pixel_kpc} kpc, B={len(th_np)}")
+    gp, gkin = gk.Grid(PHOT, max_batch=8), gk.Grid(KIN, max_batch=8)
+    gp.set_data(dp, ep)
+    gkin.set_data(dk, ek)
+    th = torch.tensor(th_np, device="cuda")
+    hs = [gp.handle, gkin.handle]
+    ll = gk.loglike_joint(hs, th).cpu().numpy()
+    again = gk.loglike_joint(hs, th).cpu().numpy()
+    assert np.array_equal(ll, again)
+    grad = torch.zeros_like(th)
+    lg = gk.loglike_joint(hs, th, grad=grad).cpu().numpy()
+    np.testing.assert_array_equal(lg, ll)
+    # the joint value is the sum of the per-grid values
+    sep = gp.loglike(th).cpu().numpy() + gkin.loglike(th).cpu().numpy()
+    np.testing.assert_allclose(ll, sep, rtol=1e-13, atol=1e-9)
+    g = grad.cpu().numpy()
+    worst = 0.0
+    for k, t in enumerate(th_np):
+        lo = M.loglike_joint([PHOT, KIN], [dp, dk], [ep, ek], t)
+        tol = LOGL_ATOL + (0.0 if k == 0 else logl_bound(PHOT, dp, ep, t) + logl_bound(KIN, dk, ek, t))
+        assert abs(ll[k] - lo) <= tol, (k, ll[k], lo, tol)
+        if k < 3:
+            ref = M.grad_joint_complex_step([PHOT, KIN], [dp, dk], [ep, ek], t)
+            worst = max(worst, check_grad(g[k], ref, f"joint row {k}"))
+        if k == 0:
+            say(f"  truth: joint logL gpu {ll[k]:.6f} oracle {lo:.6f}")
+    say(f"  worst relative gradient error {worst:.2e}")
+    gp.close()
+    gkin.close()
+
+
+def test_joint_of_split_maps_equals_one_grid(gk):
+    spec = W.GridSpec(33, 29, 0.15, 3, 1.06, W.BULGE_JAFFE, 2, W.HALO_NFW)
+    rng = np.random.default_rng(zlib.crc32(b"joint-split"))
+    truth = W.draw_thetas(spec, 1, rng)[0]
+    data, err = M.synthetic_data(spec, truth, W.elliptical_mask(spec.nx, spec.ny, 14.0, 12.0), rng)
+    th = torch.tensor(np.vstack([truth[None], W.draw_thetas(spec, 7, rng)]), device="cuda")
+    one = gk.Grid(spec, max_batch=8)
+    one.set_data(data, err)
+    ea, eb = err.copy(), err.copy()
+    ea[1:] = 0.0
+    eb[0] = 0.0
+    ga, gb = gk.Grid(spec, max_batch=8), gk.Grid(spec, max_batch=8)
+    ga.set_data(data, ea)
+    gb.set_data(data, eb)
+    l1, g1 = one.loglike_grad(th)
+    g2 = torch.zeros_like(th)
+    l2 = gk.loglike_joint([ga.handle, gb.handle], th, grad=g2)
+    np.testing.assert_allclose(l2.cpu().numpy(), l1.cpu().numpy(), rtol=1e-13, atol=1e-9)
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    for k in range(th.shape[0]):
+        # the two adjoints round differently in FP32 per lattice point
+        assert np.all(np.abs(g2[k] - g1[k]) <= 1e-5 * np.abs(g1[k]) + 1e-5 * np.linalg.norm(g1[k])), k
+    for g in (one, ga, gb):
+        g.close()
+
+
+def test_joint_argument_errors(gk):
+    a = gk.Grid(KIN, max_batch=4)
+    other = gk.Grid(W.GridSpec(19, 17, 0.2, 3, 1.0, 1, 1, W.HALO_NFW), max_batch=4)
+    th = torch.zeros(2, KIN.n_params, dtype=torch.float64, device="cuda")
+    with pytest.raises(gk.GalkinError) as e:                 # no data yet
+        gk.loglike_joint([a.handle], th)
+    assert e.value.code == gk.GK_ESTATE
+    ones = np.ones((4, KIN.ny, KIN.nx))
+    a.set_data(ones, ones)
+    other.set_data(ones, ones)
+    with pytest.raises(gk.GalkinError) as e:                 # another component set
+        gk.loglike_joint([a.handle, other.handle], th)
+    assert e.value.code == gk.GK_EINVAL
+    with pytest.raises(gk.GalkinError) as e:                 # the same grid twice
+        gk.loglike_joint([a.handle, a.handle], th)
+    assert e.value.code == gk.GK_EINVAL
+    with pytest.raises(gk.GalkinError) as e:                 # no grid
+        gk.loglike_joint([], th)
+    assert e.value.code == gk.GK_EINVAL
+    a.close()
+    other.close()

@@ -92,6 +92,9 @@ CASES = {
                                      psf_mode=W.PSF_LUMINOSITY), None, 4),
     "lw_nobulge_s5": (W.GridSpec(19, 21, 0.25, 5, 0.8, 0, 2, W.HALO_NONE, psf_mode=W.PSF_LUMINOSITY),
                       None, 4),
+    # centre parameters in a shared frame of 2.5x larger pixels, offset
+    "frame_scaled": (W.GridSpec(31, 27, 0.1, 3, 1.0, 1, 1, W.HALO_NFW, frame_px_kpc=0.25, frame_dx=1.5,
+                                frame_dy=-2.0), (12.0, 10.0), 4),
 }
 
 
@@ -227,7 +230,8 @@ GRAD_RTOL, GRAD_NORM_TOL = 1e-3, 1e-4
 
 def check_grad(got, ref, tag):
     tol = GRAD_RTOL * np.abs(ref) + GRAD_NORM_TOL * np.linalg.norm(ref)
-    bad = np.abs(got - ref) > tol
+    assert np.isfinite(got).all() and np.isfinite(ref).all(), f"{tag}: non-finite gradient {got}"
+    bad = ~(np.abs(got - ref) <= tol)
     assert not bad.any(), f"{tag}: params {np.nonzero(bad)[0]}: gpu {got[bad]} oracle {ref[bad]}"
     return float(np.max(np.abs(got - ref) / (np.abs(ref) + np.linalg.norm(ref))))
 
@@ -236,7 +240,7 @@ def check_grad(got, ref, tag):
                                     ("nobulge_2d_nohalo", 3), ("bulge_only_s5", 3), ("no_psf", 3),
                                     ("realistic", 2), ("jaffe_2d_nfw", 3), ("jaffe_only_s5", 2),
                                     ("jaffe_1d_hq_s1", 2), ("lw_2d_nfw", 3), ("lw_jaffe_1d_hq_s1", 2),
-                                    ("lw_nobulge_s5", 2)])
+                                    ("lw_nobulge_s5", 2), ("frame_scaled", 3)])
 def test_gradient_matches_oracle(gk, name, n):
     spec, data, err, thetas = make_case(name)
     thetas = thetas[:n]
