@@ -43,6 +43,9 @@ WORKLOAD_TEXT = {
               "8192 parameter vectors",
     "jaffe": "realistic IFU cube with a Jaffe bulge (Appendix B): 80x80 spaxels, 3x3 supersampling, "
              "PSF FWHM 2.5 px, Jaffe bulge + 2 discs + NFW halo (17 params), 1024 parameter vectors",
+    "lw": "realistic IFU cube with the PSF applied to the luminosity-weighted moments (B, B v, "
+          "B (sigma^2 + v^2), mass): 80x80 spaxels, 3x3 supersampling, PSF FWHM 2.5 px, 4 components "
+          "(17 params), 1024 parameter vectors",
 }
 
 
@@ -57,6 +60,8 @@ def flops_per_point(spec) -> int:
     f += 32 * spec.n_discs                   # exp, B, light sums, phi polynomial, v_c^2
     f += {0: 0, 1: 6, 2: 19}[spec.halo]      # Hernquist / NFW v_c^2
     f += 13                                  # v_int, light-weighted v, sigma, <L/M>
+    if getattr(spec, "psf_mode", 0) == 1:
+        f += 6                               # moments B v, B (sigma^2 + v^2), B / <L/M>
     return f
 
 
@@ -64,12 +69,14 @@ def stencil_pad(spec) -> int:
     return int(math.floor(3.0 * spec.psf_sigma_px * spec.supersample))
 
 
-def flops_per_pixel(spec) -> int:
+def flops_per_pixel(spec, n_maps: int = 4) -> int:
     """Separable circular stencil: per map, s lattice rows of incremental
     horizontal sums (1 + 3 pad) plus (2 pad + 1) weighted pushes (2 each),
-    then the residual and FP64 chi^2 term (~5)."""
+    then the residual and FP64 chi^2 term (~5); the moment ratios of the
+    luminosity-weighted mode add ~7 per pixel."""
     s, pad = spec.supersample, stencil_pad(spec)
-    return 4 * (s * (1 + 3 * pad) + 2 * (2 * pad + 1) + 5) + 1
+    lw = 7 if getattr(spec, "psf_mode", 0) == 1 else 0
+    return n_maps * (s * (1 + 3 * pad) + 2 * (2 * pad + 1) + 5) + 1 + lw
 
 
 def needed_points(spec, mask) -> int:
@@ -383,6 +390,112 @@ def bench_nested(args):
 
 
 # ----------------------------------------------------------------------------
+# one galaxy on two pixelisations: joint likelihood over two grids
+# ----------------------------------------------------------------------------
+def bench_multires(args):
+    import torch
+    import workloads as W
+    import paper_2205_06819_amd as gk
+
+    wp, wk = W.multires_pair()
+    B = wp.batch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rng = np.random.default_rng(wp.seed)
+    truth = W.draw_thetas(wk.spec, 1, rng)
+    thetas = W.draw_thetas(wk.spec, B, rng)
+    th = torch.tensor(thetas, dtype=torch.float64, device=dev)
+    t0 = torch.tensor(truth, dtype=torch.float64, device=dev)
+    grids, datas, carried = [], [], [(0,), (1, 2, 3)]
+    for w, maps_kept in zip((wp, wk), carried):
+        g = gk.Grid(w.spec, max_batch=B)
+        maps = g.maps(t0)[0].cpu().numpy()
+        err = W.error_maps(maps, w.mask())
+        for m in range(4):
+            if m not in maps_kept:
+                err[m] = 0.0          # this pixelisation does not carry map m
+        data = W.noisy_data(maps, err, rng)
+        g.set_data(data, err)
+        grids.append(g)
+        datas.append((data, err))
+    hs = [g.handle for g in grids]
+    out = torch.empty(B, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tuned = None
+    if args.tune:
+        from paper_2205_06819_amd import autotune
+        tuned = [list(autotune.tune(g, th, reps=2)[:3]) for g in grids]
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_step = timed(lambda: gk.loglike_joint(hs, th, out), args.steps)
+    logl = out.cpu().numpy()
+    # per-grid launches (the same kernels the joint call enqueues), for the roofline
+    per = [timed(lambda g=g: g.loglike(th, out), args.steps) for g in grids]
+    grad_info = {}
+    if not args.no_grad:
+        gbuf = torch.empty(B, th.shape[1], dtype=torch.float64, device=dev)
+        msg = timed(lambda: gk.loglike_joint(hs, th, out, grad=gbuf), max(1, args.steps // 2))
+        grad_info = {"grad_ms_per_step": round(msg, 4), "grad_evals_per_s": round(B / (msg * 1e-3), 1)}
+    flops = []
+    for w, maps_kept in zip((wp, wk), carried):
+        n_need = needed_points(w.spec, w.mask())
+        flops.append(n_need * flops_per_point(w.spec) + int(w.mask().sum()) * flops_per_pixel(w.spec, len(maps_kept)))
+    dom = int(np.argmax(per))
+    wd = (wp, wk)[dom]
+    achieved = flops[dom] * B / (per[dom] * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": f"gk::fwd_kernel<{wd.spec.bulge},{wd.spec.n_discs},{wd.spec.halo},0> ({wd.name})",
+            "flop_per_vector": flops[dom], "per_grid_ms": [round(x, 4) for x in per]}
+    cpu = None
+    if not args.no_cpu:
+        # the oracle's joint likelihood on a bounded sample of the batch
+        from oracle import model as M
+        n, t_start = 0, time.perf_counter()
+        specs = [wp.spec, wk.spec]
+        dd = [d.astype(np.float32).astype(np.float64) for d, _ in datas]
+        ee = [e.astype(np.float32).astype(np.float64) for _, e in datas]
+        vals = []
+        while n < B and time.perf_counter() - t_start < args.cpu_budget:
+            vals.append(M.loglike_joint(specs, dd, ee, thetas[n]))
+            n += 1
+        wall = time.perf_counter() - t_start
+        rel = np.abs(np.array(vals) - logl[:n]) / np.maximum(1.0, np.abs(np.array(vals)))
+        cpu = {"value": round(n / wall, 3), "unit": "likelihood evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n} of the {B} parameter vectors, one process",
+               "max_rel_diff_vs_gpu": float(rel.max())}
+    line = {
+        "metric": "likelihood evals/s and gradient evals/s (params×spaxels/s), batched vs plain",
+        "value": round(B / (ms_step * 1e-3), 1), "unit": "likelihood evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "one galaxy on two pixelisations (joint likelihood): B on 160x160 pixels "
+                               "of 0.25 arcsec, no supersampling, PSF FWHM 4 px; v, sigma, M/L on the "
+                               "realistic 80x80 IFU grid (3x3 supersampling, PSF FWHM 2.5 px); 4 "
+                               "components (17 params), 1024 parameter vectors",
+                   "batch": B, "launch_shapes": tuned or "library default"},
+        **grad_info,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    for g in grids:
+        g.close()
+
+
+# ----------------------------------------------------------------------------
 # data preparation (colour-M/L maps): an HBM-bound elementwise kernel
 # ----------------------------------------------------------------------------
 def bench_prep(args):
@@ -437,7 +550,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="realistic",
-                    help="realistic (default), tiny, adjoint, stress, jaffe, uneven (many galaxies) "
+                    help="realistic (default), tiny, adjoint, stress, jaffe, lw (luminosity-weighted "
+                         "PSF), uneven (many galaxies), multires (one galaxy on two pixelisations), "
                          "nested (the nested sampler driving the likelihood) or prep (colour-M/L maps)")
     ap.add_argument("--hmc-steps", type=int, default=0,
                     help="also time one graph-captured leapfrog trajectory of this many steps")
@@ -463,6 +577,8 @@ def main():
         return bench_nested(args)
     if args.workload == "prep":
         return bench_prep(args)
+    if args.workload == "multires":
+        return bench_multires(args)
 
     import torch
     import workloads as W

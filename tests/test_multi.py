@@ -156,3 +156,31 @@ def test_multi_argument_errors(gk):
     out = gk.loglike_multi([], th, [0])
     assert out.numel() == 0
     g.close()
+
+
+def test_multi_follows_new_data_with_fewer_maps(gk):
+    """set_data that drops maps (zero errors) changes which maps a grid
+    convolves; a cached many-grid plan must follow."""
+    say("[multi] data with fewer maps after a cached plan")
+    specs = SPECS[:3]
+    grids, truths, datas = build(gk, specs)
+    stride = max(s.n_params for s, _ in specs)
+    th_np, offs = stacked_thetas(specs, truths, stride, seed=5)
+    th = torch.tensor(th_np, device="cuda")
+    handles = [g.handle for g in grids]
+    gk.loglike_multi(handles, th, offs)
+    data, err = datas[0]
+    err = err.copy()
+    err[1:] = 0.0                     # B only
+    grids[0].set_data(data, err)
+    got = gk.loglike_multi(handles, th, offs).cpu().numpy()
+    for k, ((spec, n), g) in enumerate(zip(specs, grids)):
+        if n == 0:
+            continue
+        sl = slice(offs[k], offs[k + 1])
+        ref = g.loglike(th[sl, :spec.n_params].contiguous()).cpu().numpy()
+        np.testing.assert_allclose(got[sl], ref, rtol=1e-12, atol=1e-9, err_msg=f"grid {k}")
+    lo = M.loglike(specs[0][0], data, err, th_np[0][:specs[0][0].n_params])
+    assert abs(got[0] - lo) <= 1e-3, (got[0], lo)
+    for g in grids:
+        g.close()

@@ -185,7 +185,7 @@ SEED0 = 20220505
 
 
 def workload(name: str) -> Workload:
-    """The benchmark workloads, by name: tiny, realistic, adjoint, stress, jaffe."""
+    """The benchmark workloads, by name: tiny, realistic, adjoint, stress, jaffe, lw."""
     if name == "tiny":
         spec = GridSpec(40, 40, PK_50MPC, 1, 1.5, BULGE_HERNQUIST, 1, HALO_NFW)
         return Workload(name, spec, 64, None, SEED0 + 0)
@@ -199,6 +199,11 @@ def workload(name: str) -> Workload:
         # the realistic IFU cube with the Appendix-B (Jaffe) bulge
         spec = GridSpec(80, 80, PK_50MPC, 3, SIGMA_FWHM_2P5, BULGE_JAFFE, 2, HALO_NFW)
         return Workload(name, spec, 1024, (38.0, 33.6), SEED0 + 5)
+    if name == "lw":
+        # the realistic IFU cube, PSF applied to the luminosity-weighted moments
+        spec = GridSpec(80, 80, PK_50MPC, 3, SIGMA_FWHM_2P5, BULGE_HERNQUIST, 2, HALO_NFW,
+                        psf_mode=PSF_LUMINOSITY)
+        return Workload(name, spec, 1024, (38.0, 33.6), SEED0 + 6)
     if name == "stress":
         spec = GridSpec(300, 300, PK_50MPC, 5, SIGMA_FWHM_4, BULGE_HERNQUIST, 2, HALO_NFW)
         return Workload(name, spec, 8192, None, SEED0 + 4, gradient=True)
@@ -223,3 +228,16 @@ def uneven_galaxies(n_gal: int = 256, theta_per_gal: int = 128,
         spec = GridSpec(n, n, PK_50MPC, 3, SIGMA_FWHM_2P5, bulge, nd, halo)
         out.append(Workload(f"gal{g}", spec, theta_per_gal, None, seed * 1000 + g))
     return out
+
+
+def multires_pair():
+    """One galaxy seen on two pixelisations: photometry (B) on a 160x160 grid
+    of 0.25 arcsec pixels with 1 arcsec seeing and no supersampling, and the
+    kinematic and M/L maps on the realistic 80x80 IFU grid.  The centre
+    parameters are in the IFU grid's pixels.  Returns (photometry workload,
+    IFU workload); the photometric grid's mask is the IFU mask scaled by 2."""
+    phot = GridSpec(160, 160, PK_50MPC / 2.0, 1, SIGMA_FWHM_4, BULGE_HERNQUIST, 2, HALO_NFW,
+                    frame_px_kpc=PK_50MPC)
+    kin = GridSpec(80, 80, PK_50MPC, 3, SIGMA_FWHM_2P5, BULGE_HERNQUIST, 2, HALO_NFW)
+    return (Workload("multires-phot", phot, 1024, (76.0, 67.2), SEED0 + 7),
+            Workload("multires-ifu", kin, 1024, (38.0, 33.6), SEED0 + 7))
