@@ -37,6 +37,8 @@ SPECS = [
     (W.GridSpec(21, 20, 0.2, 3, 0.0, 1, 1, W.HALO_NFW), 4),
     (W.GridSpec(70, 66, 0.12, 3, 1.06, 1, 2, W.HALO_NFW), 3),   # wider than one band
     (W.GridSpec(26, 28, 0.2, 3, 1.06, W.BULGE_JAFFE, 2, W.HALO_NFW), 4),
+    (W.GridSpec(30, 24, 0.15, 3, 1.1, 1, 2, W.HALO_NFW, psf_mode=W.PSF_LUMINOSITY), 3),
+    (W.GridSpec(22, 26, 0.1, 1, 1.4, 1, 1, W.HALO_HERNQUIST, frame_px_kpc=0.2, frame_dx=0.5), 2),
 ]
 
 
