@@ -717,11 +717,25 @@ __global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
             const int klo = max(0, (int)floorf((float)(-A - rx + s - 1) * inv_s + 1e-4f));
             const int khi = min(D, (int)floorf((float)(A - rx) * inv_s + 1e-4f));
             const int ccl = max(0, cq - khi), cch = min(NC - 1, cq - klo);
-            for (int cc = ccl; cc <= cch; ++cc) {
-                int aa = x - cc * s - pad;
-                aa = aa < 0 ? -aa : aa;
-                const float w = gb * s_gw[aa];
-                const float4 fb = s_fb[jj * NC + cc];
+            const float4* fbr = s_fb + jj * NC;
+            int cc = ccl;
+            int t0 = x - cc * s - pad;
+            for (; cc < cch; cc += 2, t0 -= 2 * s) {
+                // two taps per trip: both pairs of LDS reads are in flight together
+                const int a0 = t0 < 0 ? -t0 : t0;
+                const int t1 = t0 - s, a1 = t1 < 0 ? -t1 : t1;
+                const float g0 = s_gw[a0], g1 = s_gw[a1];
+                const float4 b0 = fbr[cc], b1 = fbr[cc + 1];
+                const float w0 = gb * g0, w1 = gb * g1;
+                f.x = fmaf(w1, b1.x, fmaf(w0, b0.x, f.x));
+                f.y = fmaf(w1, b1.y, fmaf(w0, b0.y, f.y));
+                f.z = fmaf(w1, b1.z, fmaf(w0, b0.z, f.z));
+                f.w = fmaf(w1, b1.w, fmaf(w0, b0.w, f.w));
+            }
+            if (cc == cch) {
+                const int a0 = t0 < 0 ? -t0 : t0;
+                const float w = gb * s_gw[a0];
+                const float4 fb = fbr[cc];
                 f.x = fmaf(w, fb.x, f.x);
                 f.y = fmaf(w, fb.y, f.y);
                 f.z = fmaf(w, fb.z, f.z);
