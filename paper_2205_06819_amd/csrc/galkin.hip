@@ -174,8 +174,10 @@ __device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rs
 }
 
 // One parameter vector (row b) on one band of one grid.  load_tables = false
-// when the caller already staged the special-function tables in LDS.
-template <int BULGE, int NDISC, int HALO, int MODE>
+// when the caller already staged the special-function tables in LDS.  LW = 1:
+// the PSF averages luminosity-weighted moments (a compile-time switch, so the
+// map-averaging instantiations do not carry its registers).
+template <int BULGE, int NDISC, int HALO, int MODE, int LW>
 __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const int band, float* smem,
                                          const bool load_tables) {
     const int tid = threadIdx.x, BS = blockDim.x;
@@ -190,7 +192,7 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     const int ubase = c0 * s + hs;                  // lattice column of local column 0
     const int nfrm = nfr_max(a.band_h, s, pad);
     const int RS = a.gsub * s;
-    const Layout L = make_layout(RS, a.xw, nfrm, a.band_h, G.lw ? 8 * a.gsub * a.band_w : 0);
+    const Layout L = make_layout(RS, a.xw, nfrm, a.band_h, LW ? 8 * a.gsub * a.band_w : 0);
     float* s_tab = smem + L.tab;
     float* s_rows = smem + L.rows;
     double* s_red = (double*)(smem + L.red);
@@ -316,7 +318,7 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
             float fB, fV, fS, fL;
             point_model<BULGE, NDISC, HALO>(tc, T, du, dv, fB, fV, fS, fL);
             float* row = s_rows + lr * 4 * XW + x;
-            if (G.lw) {         // light, first and second velocity moments, mass
+            if (LW) {         // light, first and second velocity moments, mass
                 row[0] = fB;
                 row[XW] = fB * fV;
                 row[2 * XW] = fB * fmaf(fS, fS, fV * fV);
@@ -351,7 +353,7 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
                 }
 #undef GK_SUB
                 const int jj = q - D;                   // pixel row completed by this step
-                if (jj >= 0 && G.lw) {
+                if (jj >= 0 && LW) {
                     if (pact) s_fin[(k * 4 + pm) * a.band_w + pc] = acc[D] * invW;
                 } else if (jj >= 0) {
                     const float F = acc[D] * invW;
@@ -373,7 +375,7 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
                 }
             }
         }
-        if (G.lw) {
+        if (LW) {
             // luminosity-weighted moments: every pixel's four PSF moments are in
             // s_fin; each (map, column) thread forms its own observable from them
             __syncthreads();
@@ -475,10 +477,10 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     }
 }
 
-template <int BULGE, int NDISC, int HALO, int MODE>
+template <int BULGE, int NDISC, int HALO, int MODE, int LW>
 __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
     extern __shared__ __align__(16) float smem[];
-    fwd_band<BULGE, NDISC, HALO, MODE>(a, blockIdx.x / a.nbands, blockIdx.x % a.nbands, smem, true);
+    fwd_band<BULGE, NDISC, HALO, MODE, LW>(a, blockIdx.x / a.nbands, blockIdx.x % a.nbands, smem, true);
 }
 
 // ============================================================================
@@ -493,6 +495,7 @@ typedef const __attribute__((address_space(4))) int* const_word_ptr;
 
 constexpr int MULTI_BS = 256;   // threads per workgroup of the many-grid launch
 
+template <int LW>
 __global__ void __launch_bounds__(MULTI_BS) multi_kernel(const FwdArgs* __restrict__ grids,
                                                          const int4* __restrict__ items,
                                                          const double* theta, int stride, double* logL) {
@@ -507,7 +510,7 @@ __global__ void __launch_bounds__(MULTI_BS) multi_kernel(const FwdArgs* __restri
     switch (comp) {
 #define GK_MCASE(BU, ND, HA)                                                                   \
     case BU * 100 + ND * 10 + HA:                                                              \
-        fwd_band<BU, ND, HA, MODE_LOGL>(a, row, band, smem, true);                              \
+        fwd_band<BU, ND, HA, MODE_LOGL, LW>(a, row, band, smem, true);                          \
         break;
         GK_MCASE(1, 0, 0) GK_MCASE(1, 0, 1) GK_MCASE(1, 0, 2)
         GK_MCASE(1, 1, 0) GK_MCASE(1, 1, 1) GK_MCASE(1, 1, 2)
@@ -1016,7 +1019,10 @@ static hipError_t launch_fwd(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, i
     const dim3 grid((unsigned)(B * c.nbands)), block((unsigned)c.BS);
 #define GK_LAUNCH(BU, ND, HA)                                                                    \
     if (bulge == BU && nd == ND && halo == HA) {                                                  \
-        hipLaunchKernelGGL((fwd_kernel<BU, ND, HA, MODE>), grid, block, c.lds, st, a);           \
+        if (a.geo.lw)                                                                             \
+            hipLaunchKernelGGL((fwd_kernel<BU, ND, HA, MODE, 1>), grid, block, c.lds, st, a);    \
+        else                                                                                      \
+            hipLaunchKernelGGL((fwd_kernel<BU, ND, HA, MODE, 0>), grid, block, c.lds, st, a);    \
         return hipGetLastError();                                                                 \
     }
     GK_LAUNCH(1, 0, 0) GK_LAUNCH(1, 0, 1) GK_LAUNCH(1, 0, 2)
@@ -1082,6 +1088,7 @@ struct MultiPlan {
     FwdArgs* d_args = nullptr;
     int4* d_items = nullptr;
     int n_items = 0, lds = 0;
+    int n_items_lw = 0;             // the last n_items_lw items belong to luminosity-weighted grids
 };
 
 static std::mutex g_plan_mu;
@@ -1162,10 +1169,20 @@ static int build_plan(int device, const gk_grid* const* grids, int n, const int*
             for (int r = 0; r < rows; ++r) items.push_back({cost, make_int4(i, r, band, offs[i])});
         }
     }
-    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    // map-averaging items first, then the luminosity-weighted ones (a launch
+    // each), each part in decreasing cost order
+    std::stable_sort(items.begin(), items.end(), [&](const Item& x, const Item& y) {
+        const int lx = grids[x.it.x]->geo.lw, ly = grids[y.it.x]->geo.lw;
+        return lx != ly ? lx < ly : x.cost > y.cost;
+    });
     std::vector<int4> it(items.size());
-    for (size_t k = 0; k < items.size(); ++k) it[k] = items[k].it;
+    int n_lw = 0;
+    for (size_t k = 0; k < items.size(); ++k) {
+        it[k] = items[k].it;
+        n_lw += grids[items[k].it.x]->geo.lw;
+    }
     p->n_items = (int)it.size();
+    p->n_items_lw = n_lw;
     p->lds = lds;
     if (hipMalloc((void**)&p->d_args, sizeof(FwdArgs) * n) != hipSuccess ||
         hipMalloc((void**)&p->d_items, sizeof(int4) * std::max<size_t>(1, it.size())) != hipSuccess) {
@@ -1623,9 +1640,13 @@ int loglike_multi(const gk_grid_t* grids, int n_gal, const double* theta, const 
             g_plans.push_back(p);
         }
     }
-    if (p->n_items == 0) return GK_OK;
-    hipLaunchKernelGGL(multi_kernel, dim3((unsigned)p->n_items), dim3(MULTI_BS), p->lds, st, p->d_args, p->d_items,
-                       theta, stride, logL);
+    const int n0 = p->n_items - p->n_items_lw;
+    if (n0 > 0)
+        hipLaunchKernelGGL(multi_kernel<0>, dim3((unsigned)n0), dim3(MULTI_BS), p->lds, st, p->d_args, p->d_items,
+                           theta, stride, logL);
+    if (p->n_items_lw > 0)
+        hipLaunchKernelGGL(multi_kernel<1>, dim3((unsigned)p->n_items_lw), dim3(MULTI_BS), p->lds, st, p->d_args,
+                           p->d_items + n0, theta, stride, logL);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(GK_EHIP, "many-grid launch failed: %s", hipGetErrorString(e));
     return GK_OK;
