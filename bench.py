@@ -456,7 +456,7 @@ def bench_multires(args):
     achieved = flops[dom] * B / (per[dom] * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "kernel": f"gk::fwd_kernel<{wd.spec.bulge},{wd.spec.n_discs},{wd.spec.halo},0> ({wd.name})",
+            "kernel": f"gk::fwd_kernel<{wd.spec.bulge},{wd.spec.n_discs},{wd.spec.halo},0,{wd.spec.psf_mode}> ({wd.name})",
             "flop_per_vector": flops[dom], "per_grid_ms": [round(x, 4) for x in per]}
     cpu = None
     if not args.no_cpu:
@@ -707,7 +707,7 @@ def main():
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
             "frac_of_nonpacked_fp32": round(achieved / PEAK_FP32_NONPACKED, 4),
-            "kernel": f"gk::fwd_kernel<{spec.bulge},{spec.n_discs},{spec.halo},0>",
+            "kernel": f"gk::fwd_kernel<{spec.bulge},{spec.n_discs},{spec.halo},0,{spec.psf_mode}>",
             "flop_per_vector": flop_theta,
             "per_unit": {"lattice_points": n_need, "flop_per_point": flops_per_point(spec),
                          "valid_spaxels": n_valid, "flop_per_spaxel": flops_per_pixel(spec)}}
