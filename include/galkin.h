@@ -22,7 +22,8 @@
  *    entries) are not errors: they give logL = -inf and a zero gradient row.
  *  - "device" pointers are HIP device memory of the grid's device; the caller
  *    owns them.  The library keeps no caller pointer after a call returns.
- *  - hot-path calls (loglike_batch, loglike_grad_batch, eval_maps) are
+ *  - hot-path calls (loglike_batch, loglike_grad_batch, eval_maps,
+ *    loglike_joint, hmc_leapfrog) are
  *    asynchronous on the given hipStream_t (NULL = default stream): they do
  *    not allocate, synchronise or read device memory on the host, so they
  *    may be captured in a HIP graph.  Calls that share one grid handle must
@@ -34,8 +35,10 @@
  *                       (Hernquist, Sec. 2.2, or Jaffe, Appendix B)
  *    disc j (1..n)      log10 Mdj [Msun], Rdj [kpc], (M/L)dj, kj
  *    halo               log10 Mh [Msun], then c (NFW) or Rh [kpc] (Hernquist)
- * The galaxy centre is the grid centre ((nx-1)/2, (ny-1)/2) plus (x0, y0);
- * the position angle is counter-clockwise from +x (x = column index).
+ * The galaxy centre is the grid centre ((nx-1)/2, (ny-1)/2) plus (x0, y0)
+ * (scaled and offset by the descriptor's frame fields when the centre
+ * parameters are shared by several pixelisations); the position angle is
+ * counter-clockwise from +x (x = column index).
  */
 #ifndef GALKIN_H
 #define GALKIN_H
@@ -100,7 +103,10 @@ int n_params(gk_grid_t grid);
  * A pixel is masked in a map when its err is <= 0 or not finite, or its
  * value is not finite.  on_device != 0 means both pointers are device
  * memory.  The data are copied (the caller keeps ownership); this call is
- * synchronous with respect to the given stream and may be repeated. */
+ * synchronous with respect to the given stream and may be repeated.  A map
+ * with no valid pixel is not convolved by the log-likelihood calls (a grid
+ * that carries only some maps pays only for those); when that set changes,
+ * the grid's cached many-grid plans are dropped (which synchronises). */
 int set_data(gk_grid_t grid, const float* value, const float* err, int on_device,
              void* hip_stream);
 
@@ -162,7 +168,8 @@ int loglike_joint(const gk_grid_t* grids, int n_grids, const double* theta, int 
  * (device float64 [rows][stride], stride >= every grid's P) belong to galaxy g
  * and number at most that grid's max_batch; logL: device float64 [rows].
  * Each workgroup evaluates one (galaxy, row, pixel band) item; items are
- * dispatched in decreasing cost order.  The first call with a given (grids, theta_offset,
+ * dispatched in decreasing cost order (the items of luminosity-weighted
+ * grids, GK_PSF_LUMINOSITY, in a second launch of their own).  The first call with a given (grids, theta_offset,
  * launch shapes) builds and uploads that work plan (allocating and
  * synchronising); repeated calls with the same arguments only enqueue the
  * launch and may then be captured in a HIP graph.  A destroyed grid's plans
