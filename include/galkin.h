@@ -208,6 +208,13 @@ int brightness_errors(const float* B, int n, double rel, double floor_frac, floa
  * 64 there). */
 int set_launch_shape(gk_grid_t grid, int batch_min, int band_h, int band_w, int steps);
 
+/* The launch shape calls with B parameter vectors use: band_h, band_w
+ * (pixels, clipped to the grid) and steps (pixel rows per model phase, 0 =
+ * automatic), written to host ints — the library default unless
+ * set_launch_shape installed a rule for that batch size.  For autotuners,
+ * which time this shape alongside their own candidates. */
+int get_launch_shape(gk_grid_t grid, int B, int* band_h, int* band_w, int* steps);
+
 /* Message describing the last error returned on the calling thread. */
 const char* last_error(void);
 

@@ -28,7 +28,7 @@ GK_HALO_NONE, GK_HALO_HERNQUIST, GK_HALO_NFW = 0, 1, 2
 GK_PSF_MAPS, GK_PSF_LUMINOSITY = 0, 1
 
 EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",
-           "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "loglike_joint", "ml_from_colour",
+           "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "loglike_joint", "get_launch_shape", "ml_from_colour",
            "brightness_errors", "last_error")
 
 
@@ -66,6 +66,7 @@ def _load() -> ctypes.CDLL:
     lib.hmc_leapfrog.argtypes = [vp, vp, vp, vp, d, i, i, i, vp, vp, vp]
     lib.loglike_multi.argtypes = [vp, i, vp, vp, i, vp, vp, vp]
     lib.loglike_joint.argtypes = [vp, i, vp, i, i, vp, vp, vp]
+    lib.get_launch_shape.argtypes = [vp, i, vp, vp, vp]
     lib.ml_from_colour.argtypes = [vp, vp, vp, vp, i, d, d, d, vp, vp, vp]
     lib.brightness_errors.argtypes = [vp, i, d, d, vp, vp]
     lib.last_error.restype = ctypes.c_char_p
@@ -274,6 +275,13 @@ def set_launch_shape(handle: int, batch_min: int, band_h: int, band_w: int, step
     _check(_lib.set_launch_shape(handle, int(batch_min), int(band_h), int(band_w), int(steps)))
 
 
+def get_launch_shape(handle: int, B: int):
+    """(band_h, band_w, steps) that calls with B vectors use on this grid."""
+    h, w, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lib.get_launch_shape(handle, int(B), ctypes.byref(h), ctypes.byref(w), ctypes.byref(st)))
+    return h.value, w.value, st.value
+
+
 def last_error() -> str:
     return _lib.last_error().decode()
 
@@ -314,6 +322,9 @@ class Grid:
 
     def set_launch_shape(self, batch_min, band_h, band_w, steps=0):
         set_launch_shape(self.handle, batch_min, band_h, band_w, steps)
+
+    def launch_shape(self, B):
+        return get_launch_shape(self.handle, B)
 
 
 class LogLike(torch.autograd.Function):

@@ -73,7 +73,11 @@ def tune(grid: Grid, th: torch.Tensor, reps: int = 3, use_cache: bool = True,
         grid.set_launch_shape(B, h, w, st)
         return h, w, st, ms
     out = torch.empty(B, dtype=torch.float64, device=th.device)
-    timed = []
+    # the library's own shape for this batch size is a candidate too, so the
+    # result is never slower than not tuning
+    h0, w0, st0 = grid.launch_shape(B)
+    grid.set_launch_shape(B, h0, w0, st0)
+    timed = [(_time(grid, th, out, reps), h0, w0, st0)]
     for (h, w) in (shapes or candidates(grid.nx, grid.ny, B)):
         try:
             grid.set_launch_shape(B, h, w, 0)
@@ -84,8 +88,10 @@ def tune(grid: Grid, th: torch.Tensor, reps: int = 3, use_cache: bool = True,
         raise GalkinError(-1, "no launch shape fits this grid")
     timed.sort()
     best = timed[0]
-    for (_, h, w, _) in timed[:3]:
+    for (_, h, w, st_t) in timed[:3]:
         for st in (1, 2, 3, 4):
+            if st == st_t:
+                continue
             try:
                 grid.set_launch_shape(B, h, w, st)
             except GalkinError:

@@ -1374,6 +1374,12 @@ int set_launch_shape(gk_grid_t g, int batch_min, int band_h, int band_w, int ste
     return GK_OK;
 }
 
+int get_launch_shape(gk_grid_t g, int B, int* band_h, int* band_w, int* steps) {
+    if (!g || !band_h || !band_w || !steps) return fail(GK_EINVAL, "NULL grid or output pointer");
+    if (B < 1) return fail(GK_EINVAL, "B must be >= 1");
+    return choose_rule(g, B, *band_h, *band_w, *steps);
+}
+
 int set_data(gk_grid_t g, const float* value, const float* err, int on_device, void* stream) {
     if (!g) return fail(GK_EINVAL, "grid is NULL");
     if (!value || !err) return fail(GK_EINVAL, "NULL value or err");

@@ -56,6 +56,7 @@ def test_argument_errors_without_device():
     assert lib.set_data(None, None, None, 0, None) == gk.GK_EINVAL
     assert lib.destroy_grid(None) == gk.GK_EINVAL
     assert lib.loglike_joint(None, 1, None, 1, 13, None, None, None) == gk.GK_EINVAL
+    assert lib.get_launch_shape(None, 1, None, None, None) == gk.GK_EINVAL
     assert lib.loglike_joint(None, 0, None, 1, 13, None, None, None) == gk.GK_EINVAL
     assert lib.set_launch_shape(None, 1, 1, 1, 0) == gk.GK_EINVAL
     assert lib.loglike_multi(None, -1, None, None, 13, None, None, None) == gk.GK_EINVAL

@@ -147,6 +147,7 @@ def test_band_shapes_do_not_change_results(gk, name):
     for bh, bw in [(1, 1), (5, 7), (8, 37), (23, 4), (3, 16)]:
         for steps in (0, 1, 2):            # pixel rows per model phase (0: default)
             grid.set_launch_shape(1, bh, bw, steps)
+            assert grid.launch_shape(th.shape[0]) == (min(bh, spec.ny), min(bw, spec.nx), steps)
             mp = grid.maps(th).cpu()
             ll = grid.loglike(th).cpu()
             assert torch.equal(mp, ref_maps), (bh, bw, steps)
