@@ -948,7 +948,9 @@ static int default_rules(gk_grid* g) {
     // supersampling) spends D of every band_h + D steps filling the lag, so
     // there bands grow to 16 D rows and 64 columns (measured 1.4x faster on a
     // 160 x 160 grid with D = 10)
-    const int hmax = g->D >= 9 ? 16 * g->D : 40, wmax = g->D >= 9 ? 64 : 40;
+    // (the luminosity-weighted mode, whose phases end in a moment exchange,
+    // prefers 80-row bands: measured 6 % faster on the realistic cube)
+    const int hmax = g->D >= 9 ? 16 * g->D : (g->geo.lw ? 80 : 40), wmax = g->D >= 9 ? 64 : 40;
     int bh = (ny + (ny + hmax - 1) / hmax - 1) / ((ny + hmax - 1) / hmax);
     int bw = (nx + (nx + wmax - 1) / wmax - 1) / ((nx + wmax - 1) / wmax);
     fit_shape(g, bh, bw, 0);
