@@ -1,0 +1,60 @@
+"""Host logic of bench.py (no GPU): the one-GPU contract and the algorithmic
+work counts that the roofline figures divide by."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    for args, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})):
+        e = dict(os.environ, **env)
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args, capture_output=True,
+                           text=True, env=e, timeout=120)
+        assert r.returncode == 2, (args, env, r.stdout, r.stderr)
+        assert "one GPU" in r.stderr
+        assert r.stdout.strip() == ""
+
+
+def test_realistic_work_counts():
+    wl = W.workload("realistic")
+    spec, mask = wl.spec, wl.mask()
+    assert int(mask.sum()) == 4008
+    # frame 13 + Hernquist bulge 42 + 2 discs x 32 + NFW 19 + combination 13
+    assert bench.flops_per_point(spec) == 151
+    assert bench.stencil_pad(spec) == 9
+    # 4 maps x [s (1 + 3 pad) + 2 (2 pad + 1) + 5] + 1 at s = 3, pad = 9
+    assert bench.flops_per_pixel(spec) == 4 * (3 * 28 + 38 + 5) + 1 == 509
+    assert bench.needed_points(spec, mask) == 42116
+
+
+def test_needed_points_by_brute_force():
+    """The union of the valid pixels' 3-sigma lattice discs, counted point by
+    point on a small grid."""
+    spec = W.GridSpec(9, 7, 0.2, 3, 0.8, 1, 1, W.HALO_NFW)
+    mask = W.elliptical_mask(9, 7, 3.5, 2.5)
+    s, pad = spec.supersample, bench.stencil_pad(spec)
+    r2 = 9.0 * (spec.psf_sigma_px * s) ** 2
+    pts = set()
+    for j, i in zip(*np.nonzero(mask)):
+        cy, cx = j * s + (s - 1) // 2 + pad, i * s + (s - 1) // 2 + pad
+        for b in range(-pad, pad + 1):
+            for a in range(-pad, pad + 1):
+                if a * a + b * b <= r2:
+                    pts.add((cy + b, cx + a))
+    assert bench.needed_points(spec, mask) == len(pts)
+
+
+def test_luminosity_weighted_and_single_map_counts():
+    lw = W.workload("lw").spec
+    assert bench.flops_per_point(lw) == 151 + 6
+    assert bench.flops_per_pixel(lw) == 509 + 7
+    wp, _ = W.multires_pair()
+    assert bench.flops_per_pixel(wp.spec, 1) == 1 * (1 * (1 + 3 * 5) + 2 * 11 + 5) + 1
