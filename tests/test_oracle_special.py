@@ -172,20 +172,20 @@ def test_freeman_F_library_special_case():
 
 
 # --- NFW and constants ----------------------------------------------------
-def test_nfw_circular_velocity_at_r200_and_mean_density():
-    spec_h = 0.7
-    M200 = 1e12
-    rc = M.rho_crit(spec_h)
-    r200 = (3 * M200 / (4 * math.pi * 200 * rc)) ** (1 / 3)
-    assert M200 / (4 / 3 * math.pi * r200 ** 3) == pytest.approx(200 * rc, rel=1e-12)
-    c = 10.0
-    rs = r200 / c
-    v2 = M.G_KPC * M200 * S.nfw_mu(np.array([r200 / rs]))[0] / (r200 * S.nfw_mu(np.array([c]))[0])
-    assert v2 == pytest.approx(M.G_KPC * M200 / r200, rel=1e-12)
-    # mu(x) ~ x^2/2 at small x
-    assert S.nfw_mu(np.array([1e-4]))[0] == pytest.approx(0.5e-8 * (1 - 4e-4 / 3 * 2), rel=1e-6)
+def test_nfw_mu_small_x_series():
+    # mu(x) = ln(1 + x) - x / (1 + x) = sum_n>=2 (-1)^n (n - 1) x^n / n
+    #       = x^2/2 (1 - 4x/3 + 3x^2/2 - 8x^3/5 + ...)
+    for x in (1e-4, 1e-3):
+        series = x * x / 2.0 * (1.0 - 4.0 * x / 3.0 + 1.5 * x * x - 1.6 * x ** 3)
+        assert S.nfw_mu(np.array([x]))[0] == pytest.approx(series, rel=1e-9, abs=0)
 
 
+def test_nfw_mu_is_the_enclosed_mass_of_the_nfw_density():
+    # NFW density rho ~ 1 / (x (1 + x)^2), x = r / r_s: the mass inside x is
+    # 4 pi r_s^3 rho_s int_0^x t / (1 + t)^2 dt, which must be mu(x)
+    for x in (0.01, 0.3, 1.0, 4.0, 25.0):
+        m, _ = integrate.quad(lambda t: t / (1.0 + t) ** 2, 0.0, x, epsabs=0, epsrel=1e-13, limit=200)
+        assert S.nfw_mu(np.array([x]))[0] == pytest.approx(m, rel=1e-11)
 def test_gravitational_constant_in_kpc_units():
     GM_sun = 1.32712440018e20            # m^3 s^-2 (IAU)
     kpc = 3.0856775814913673e19          # m
