@@ -1,18 +1,21 @@
 """Benchmark of the batched likelihood (and gradient) on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload realistic]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload stress]
 
-One step = one batched call over the whole batch of parameter vectors of the
-workload (B = 1024 for the realistic IFU cube: 80x80 pixels, 3x3 lattice per
-pixel, 2.5 px FWHM PSF, bulge + 2 discs + NFW halo, ~4000 valid spaxels).
-Inputs (parameters, data maps, errors) are resident in device memory before
-the timed region; the timed region is K back-to-back calls bracketed by HIP
+One step = one batched likelihood call over the whole batch of parameter
+vectors of the workload.  The default workload is the largest single-GPU
+configuration: the 300x300 high-resolution stress grid (5x5 lattice per pixel,
+4 px FWHM PSF, bulge + 2 discs + NFW halo, 8192 parameter vectors).  Inputs
+(parameters, data maps, errors) are resident in device memory before the
+timed region; the timed region is K back-to-back calls bracketed by HIP
 events on the stream the kernels run on.  Prints one JSON line.
 
 Also measured: gradient evaluations/s (loglike_grad_batch over the same
-batch), the plain form (the same kernels called once per parameter vector),
-the roofline position of the forward kernel, and the CPU oracle on a bounded
-sample of the same workload (worker processes on the host cores).
+batch), one HIP-graph-captured leapfrog trajectory (32 steps on the stress
+grid), the plain form (the same kernels called once per parameter vector),
+the roofline position of the forward and the adjoint kernel, the CPU oracle
+on a bounded sample of the same workload (worker processes on the host
+cores), and, as secondary keys, the realistic 80x80 IFU cube.
 """
 from __future__ import annotations
 
@@ -79,6 +82,28 @@ def flops_per_pixel(spec, n_maps: int = 4) -> int:
     return n_maps * (s * (1 + 3 * pad) + 2 * (2 * pad + 1) + 5) + 1 + lw
 
 
+def flops_adjoint_per_point(spec) -> int:
+    """Adjoint kernel, per needed lattice point: the point model recomputed
+    with the derivatives of its special functions, its reverse sweep into the
+    27 constant adjoints, and the transposed stencil (D + 1 horizontal taps of
+    4 FMAs, the 1/W scaling, and the vertical group sums, 4 FMAs per lag per
+    pixel column, shared by the s lattice columns of that pixel column)."""
+    f = 13 + 36                               # frame: forward, reverse
+    if spec.bulge == 1:
+        f += 69 + 36                          # Hernquist: g, h and derivatives; reverse
+    elif spec.bulge == 2:
+        f += 67 + 29                          # Jaffe
+    f += (43 + 29) * spec.n_discs             # exp, phi and phi'; reverse
+    f += {0: 0, 1: 6 + 14, 2: 32 + 8}[spec.halo]
+    f += 7 + 37                               # v_int, combination; reverse of the combination
+    if getattr(spec, "psf_mode", 0) == 1:
+        f += flops_per_point(spec) + 12       # moments need the forward model and their own reverse
+    s, pad = spec.supersample, stencil_pad(spec)
+    D = 2 * pad // s
+    f += 8 * (D + 1) + 4 + round(8 * (D + 1) / s)
+    return f
+
+
 def needed_points(spec, mask) -> int:
     """Lattice points inside the union of the 3-sigma stencils of valid pixels."""
     s, pad = spec.supersample, stencil_pad(spec)
@@ -95,11 +120,13 @@ def needed_points(spec, mask) -> int:
 
 
 def source_hash() -> str:
+    """Hash of the HIP sources (traffic counters are only valid for the kernels they were taken on)."""
     h = hashlib.sha256()
-    for f in ("galkin.hip", "gk_device.h", "gk_tables.h"):
-        p = os.path.join(ROOT, "paper_2205_06819_amd", "csrc", f)
-        if os.path.exists(p):
-            h.update(open(p, "rb").read())
+    d = os.path.join(ROOT, "paper_2205_06819_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -128,17 +155,36 @@ def _oracle_items_worker(items):
 
 
 def _host_cores() -> int:
+    """Worker processes for the oracle: the CPUs this process may run on,
+    capped at 16 (the host CPU share that goes with one GPU on the
+    benchmark machines)."""
     return max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
                       else os.cpu_count() or 1))
 
 
-def cpu_baseline(spec, data, err, thetas, budget_s: float = 20.0):
+def host_info() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "cpu_model": model,
+            "worker_cap": 16, "worker_cap_reason": "host CPU share of one GPU on the benchmark machines"}
+
+
+def cpu_baseline(spec, data, err, thetas, budget_s: float = 20.0, min_n: int = 0):
+    """The oracle's log-likelihood on a bounded sample of the batch: about
+    budget_s of CPU work per worker, at least min_n vectors."""
     import dataclasses
     from concurrent.futures import ProcessPoolExecutor
     import multiprocessing as mp
     cores = _host_cores()
     spec_d = dataclasses.asdict(spec)
-    # calibrate on one vector in this process, then size the sample to ~budget_s of CPU work
+    # calibrate on one vector in this process, then size the sample
     sys.path.insert(0, ROOT)
     from oracle import model as M
     t0 = time.perf_counter()
@@ -146,21 +192,24 @@ def cpu_baseline(spec, data, err, thetas, budget_s: float = 20.0):
     per = time.perf_counter() - t0
     n = int(max(cores, min(len(thetas), budget_s / max(per, 1e-4))))
     n = (n // cores) * cores or cores
+    n = max(n, min_n)
+    workers = min(cores, n)
     sample = thetas[:n]
-    chunks = [sample[i::cores] for i in range(cores)]
+    chunks = [sample[i::workers] for i in range(workers)]
     t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
         res = list(ex.map(_oracle_worker, [(spec_d, data, err, c) for c in chunks]))
     wall = time.perf_counter() - t0
     cpu_work = sum(r[1] for r in res)
     vals = []
     for i in range(n):
-        vals.append(res[i % cores][0][i // cores])
-    return {"value": n / wall, "unit": "likelihood evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} parameter vectors of the benchmark batch, {cores} worker processes, "
-                      f"{cpu_work:.1f} s of CPU work in {wall:.1f} s wall "
-                      f"({cpu_work / n * 1e3:.0f} ms per vector per core)",
-            "per_core_evals_per_s": n / cpu_work}, np.array(vals), n
+        vals.append(res[i % workers][0][i // workers])
+    return {"value": n / wall, "unit": "likelihood evals/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {n} parameter vectors of the benchmark batch, {workers} worker processes "
+                      f"(one vector per worker and round), {cpu_work:.1f} s of CPU work in {wall:.1f} s "
+                      f"wall ({cpu_work / n:.2f} s per vector per core); the rate is n / wall and "
+                      f"extrapolates linearly in the batch (vectors are independent)",
+            "per_core_evals_per_s": n / cpu_work, **host_info()}, np.array(vals), n
 
 
 # ----------------------------------------------------------------------------
@@ -544,48 +593,36 @@ def bench_prep(args):
 
 
 # ----------------------------------------------------------------------------
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="realistic",
-                    help="realistic (default), tiny, adjoint, stress, jaffe, lw (luminosity-weighted "
-                         "PSF), uneven (many galaxies), multires (one galaxy on two pixelisations), "
-                         "nested (the nested sampler driving the likelihood) or prep (colour-M/L maps)")
-    ap.add_argument("--hmc-steps", type=int, default=0,
-                    help="also time one graph-captured leapfrog trajectory of this many steps")
-    ap.add_argument("--plain", type=int, default=256, help="number of single-vector calls timed")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-grad", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="many-galaxy workload: skip the band-policy search")
-    ap.add_argument("--tune", action="store_true",
-                    help="single-grid workloads: autotune the launch shape (default: the library's defaults)")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="also run one 512 MiB device copy (traffic-counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(every (galaxy, parameter vector) pair is independent; see the design notes "
-              "on sharding). Run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
+# one grid, one batch: forward, gradient, plain form, roofline, oracle
+# ----------------------------------------------------------------------------
+def _events(stream):
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    if args.workload == "uneven":
-        return bench_uneven(args)
-    if args.workload == "nested":
-        return bench_nested(args)
-    if args.workload == "prep":
-        return bench_prep(args)
-    if args.workload == "multires":
-        return bench_multires(args)
 
+def _time_calls(fn, steps, warmup, stream):
+    """Mean milliseconds per call of fn over `steps` calls (after `warmup`),
+    HIP events recorded on the stream the calls enqueue on."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events(stream)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def run_single(args, name, *, steps, warmup, grad_steps, hmc_steps, plain, with_cpu, cpu_min_n=0):
     import torch
     import workloads as W
     import paper_2205_06819_amd as gk
     from paper_2205_06819_amd import autotune
 
-    wl = W.workload(args.workload)
+    wl = W.workload(name)
     spec, B = wl.spec, wl.batch
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -602,62 +639,39 @@ def main():
     th = torch.tensor(thetas, dtype=torch.float64, device=dev)
     out = torch.empty(B, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    print(f"bench: {name} grid ready ({spec.nx}x{spec.ny}, s = {spec.supersample}, B = {B})",
+          file=sys.stderr, flush=True)
 
     tuned = None
     if args.tune:
         tuned = autotune.tune(grid, th, reps=2)
-        autotune.tune(grid, th[:1], reps=20)
-        # batch sizes between 1 and B keep the default shapes
-    # ---- batched forward
-    for _ in range(args.warmup):
-        grid.loglike(th, out)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        grid.loglike(th, out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
+    # ---- batched forward (one launch of the forward kernel per step)
+    ms_step = _time_calls(lambda: grid.loglike(th, out), steps, warmup, stream)
     evals = B / (ms_step * 1e-3)
     logl_gpu = out.cpu().numpy()
+    print(f"bench: {name} forward {ms_step:.3f} ms per step", file=sys.stderr, flush=True)
 
-    # ---- gradient
-    grad_info = {}
-    if not args.no_grad:
-        try:
-            lg, g = grid.loglike_grad(th[:1])
-            ok = True
-        except gk.GalkinError:
-            ok = False
-        if ok:
-            gbuf = torch.empty(B, th.shape[1], dtype=torch.float64, device=dev)
-            for _ in range(args.warmup):
-                grid.loglike_grad(th, out, gbuf)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            for _ in range(args.steps):
-                grid.loglike_grad(th, out, gbuf)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms_grad = e0.elapsed_time(e1) / args.steps
-            grad_info = {"grad_evals_per_s": B / (ms_grad * 1e-3), "ms_per_grad_step": ms_grad}
-            if args.hmc_steps > 0:
-                grad_info.update(time_hmc(gk, grid, th, args.hmc_steps))
+    # ---- gradient (forward kernel in its adjoint-seed mode + the adjoint kernel)
+    grad_info, ms_grad = {}, None
+    if grad_steps > 0:
+        gbuf = torch.empty(B, th.shape[1], dtype=torch.float64, device=dev)
+        ms_grad = _time_calls(lambda: grid.loglike_grad(th, out, gbuf), grad_steps, 1, stream)
+        grad_info = {"grad_evals_per_s": round(B / (ms_grad * 1e-3), 1), "ms_per_grad_step": round(ms_grad, 4),
+                     "adjoint_launch_shape": list(grid.adjoint_shape())}
+        print(f"bench: {name} gradient {ms_grad:.3f} ms per step", file=sys.stderr, flush=True)
+        if hmc_steps > 0:
+            h = time_hmc(gk, grid, th, hmc_steps)
+            grad_info.update({k: (round(v, 4) if isinstance(v, float) else v) for k, v in h.items()})
 
     # ---- plain form: one call (one launch sequence) per parameter vector
-    n_plain = min(args.plain, B)
+    n_plain = min(plain, B)
     one = [th[i:i + 1] for i in range(n_plain)]
     outs = [torch.empty(1, dtype=torch.float64, device=dev) for _ in range(n_plain)]
-    for i in range(min(8, n_plain)):
-        grid.loglike(one[i], outs[i])
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(n_plain):
-        grid.loglike(one[i], outs[i])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    plain_loop_evals = n_plain / (e0.elapsed_time(e1) * 1e-3)
+
+    def plain_loop():
+        for i in range(n_plain):
+            grid.loglike(one[i], outs[i])
+    plain_loop_evals = n_plain / (_time_calls(plain_loop, 1, 1, stream) * 1e-3)
     plain_vals = torch.cat(outs).cpu().numpy()
     assert np.allclose(plain_vals, logl_gpu[:n_plain], rtol=1e-9, atol=1e-6)
     # the same per-vector calls captured once in a HIP graph (no host overhead per call)
@@ -666,36 +680,26 @@ def main():
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            for i in range(n_plain):
-                grid.loglike(one[i], outs[i])
+            plain_loop()
         torch.cuda.current_stream().wait_stream(side)
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            for i in range(n_plain):
-                grid.loglike(one[i], outs[i])
-        graph.replay()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        reps = 3
-        for _ in range(reps):
-            graph.replay()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        plain_graph_evals = reps * n_plain / (e0.elapsed_time(e1) * 1e-3)
+            plain_loop()
+        plain_graph_evals = n_plain / (_time_calls(graph.replay, 3, 1, stream) * 1e-3)
         assert np.allclose(torch.cat(outs).cpu().numpy(), logl_gpu[:n_plain], rtol=1e-9, atol=1e-6)
         del graph
     except Exception as exc:  # report, do not hide
         print(f"plain-graph timing skipped: {exc}", file=sys.stderr)
     plain_evals = max(plain_loop_evals, plain_graph_evals or 0.0)
 
-    # ---- roofline of the forward kernel (one launch per step)
+    # ---- roofline: forward kernel (one launch per step) and adjoint kernel
     n_need = needed_points(spec, mask)
     n_valid = int(mask.sum())
     flop_theta = n_need * flops_per_point(spec) + n_valid * flops_per_pixel(spec)
     achieved = flop_theta * B / (ms_step * 1e-3) / 1e12
     traffic = None
     shape = list(tuned[:3]) if tuned else None
-    tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if os.path.exists(tpath):
         try:
             t = json.load(open(tpath))
@@ -704,58 +708,142 @@ def main():
                 traffic = t.get("bytes_per_launch")
         except (OSError, ValueError):
             pass
+    lw = spec.psf_mode
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
             "frac_of_nonpacked_fp32": round(achieved / PEAK_FP32_NONPACKED, 4),
-            "kernel": f"gk::fwd_kernel<{spec.bulge},{spec.n_discs},{spec.halo},0,{spec.psf_mode}>",
+            "kernel": f"gk::fwd_kernel<{spec.bulge},{spec.n_discs},{spec.halo},0,{lw}>",
+            "kernel_ms": round(ms_step, 4),
             "flop_per_vector": flop_theta,
             "per_unit": {"lattice_points": n_need, "flop_per_point": flops_per_point(spec),
                          "valid_spaxels": n_valid, "flop_per_spaxel": flops_per_pixel(spec)}}
-
-    if args.copy_calib:
-        src_buf = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
-        dst_buf = torch.empty_like(src_buf)
-        torch.cuda.synchronize()
-        dst_buf.copy_(src_buf)
-        torch.cuda.synchronize()
-        del src_buf, dst_buf
+    roof_adj = None
+    if ms_grad is not None:
+        # the gradient step is the forward kernel in its seed mode (the forward
+        # plus 16 B of stores per pixel) followed by the adjoint kernel
+        ms_adj = ms_grad - ms_step
+        fa = flops_adjoint_per_point(spec)
+        a_ach = n_need * fa * B / (ms_adj * 1e-3) / 1e12
+        roof_adj = {"bound": "alu", "achieved": round(a_ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(a_ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                    "frac_of_nonpacked_fp32": round(a_ach / PEAK_FP32_NONPACKED, 4),
+                    "kernel": f"gk::adj_kernel<{spec.bulge},{spec.n_discs},{spec.halo},{lw}>",
+                    "kernel_ms": round(ms_adj, 4),
+                    "kernel_ms_from": "gradient step minus forward step (HIP events)",
+                    "flop_per_vector": n_need * fa,
+                    "per_unit": {"lattice_points": n_need, "flop_per_point": fa}}
 
     # ---- CPU baseline (oracle, unchanged)
     cpu = None
-    if not args.no_cpu:
+    if with_cpu:
+        print(f"bench: {name} oracle leg", file=sys.stderr, flush=True)
         cpu, cvals, n = cpu_baseline(spec, data.astype(np.float32).astype(np.float64),
                                      err.astype(np.float32).astype(np.float64), thetas,
-                                     args.cpu_budget)
+                                     args.cpu_budget, cpu_min_n)
         rel = np.abs(cvals - logl_gpu[:n]) / np.maximum(1.0, np.abs(cvals))
         cpu["max_rel_diff_vs_gpu"] = float(rel.max())
-
+    grid.close()
     P = spec.n_params
     spax = spec.nx * spec.ny
-    line = {
-        "metric": "likelihood evals/s and gradient evals/s (params×spaxels/s), batched vs plain",
-        "value": round(evals, 1),
-        "unit": "likelihood evals/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "batch": B,
+    res = {
+        "value": round(evals, 1), "ms_per_step": round(ms_step, 4),
+        "config": {"workload": WORKLOAD_TEXT.get(name, name), "batch": B,
                    "spaxels": spax, "valid_spaxels": n_valid, "params": P,
                    "supersample": spec.supersample, "psf_sigma_px": round(spec.psf_sigma_px, 5),
                    "launch_shape": list(tuned[:3]) if tuned else "library default"},
         "params_x_spaxels_per_s": round(evals * P * spax, 1),
+        "fine_points_per_s": round(evals * n_need, 1),
         "plain_evals_per_s": round(plain_evals, 1),
         "plain_host_loop_evals_per_s": round(plain_loop_evals, 1),
         "plain_graph_evals_per_s": round(plain_graph_evals, 1) if plain_graph_evals else None,
         "speedup_vs_plain": round(evals / plain_evals, 2),
-        **{k: round(v, 4) for k, v in grad_info.items()},
-        "roofline": roof,
-        "cpu_baseline": cpu,
+        **grad_info,
+        "roofline": roof, "roofline_adjoint": roof_adj, "cpu_baseline": cpu,
     }
     if "grad_evals_per_s" in grad_info:
-        line["grad_params_x_spaxels_per_s"] = round(grad_info["grad_evals_per_s"] * P * spax, 1)
+        res["grad_params_x_spaxels_per_s"] = round(grad_info["grad_evals_per_s"] * P * spax, 1)
+    return res
+
+
+# ----------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="stress",
+                    help="stress (default: 300x300, 5x5 lattice, B = 8192), realistic, tiny, adjoint, jaffe, "
+                         "lw (luminosity-weighted PSF), uneven (many galaxies), multires (one galaxy on two "
+                         "pixelisations), nested (the nested sampler driving the likelihood) or prep "
+                         "(colour-M/L maps)")
+    ap.add_argument("--hmc-steps", type=int, default=None,
+                    help="time one graph-captured leapfrog trajectory of this many steps "
+                         "(default: 32 on the stress workload, none elsewhere)")
+    ap.add_argument("--grad-steps", type=int, default=None,
+                    help="gradient calls timed (default: 3 on the stress workload, --steps elsewhere)")
+    ap.add_argument("--plain", type=int, default=256, help="number of single-vector calls timed")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="stress workload: skip the secondary realistic-cube measurement")
+    ap.add_argument("--no-tune", action="store_true", help="many-galaxy workload: skip the band-policy search")
+    ap.add_argument("--tune", action="store_true",
+                    help="single-grid workloads: autotune the launch shape (default: the library's defaults)")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run one 512 MiB device copy (the traffic-counter calibration) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(every (galaxy, parameter vector) pair is independent; see the design notes "
+              "on sharding). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calib:
+        import torch
+        src_buf = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst_buf = torch.empty_like(src_buf)
+        torch.cuda.synchronize()
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        print("copied 512 MiB", flush=True)
+        return
+    if args.workload == "uneven":
+        return bench_uneven(args)
+    if args.workload == "nested":
+        return bench_nested(args)
+    if args.workload == "prep":
+        return bench_prep(args)
+    if args.workload == "multires":
+        return bench_multires(args)
+
+    stress = args.workload == "stress"
+    hmc = args.hmc_steps if args.hmc_steps is not None else (32 if stress else 0)
+    gsteps = 0 if args.no_grad else (args.grad_steps if args.grad_steps is not None else (3 if stress else args.steps))
+    res = run_single(args, args.workload, steps=args.steps, warmup=args.warmup, grad_steps=gsteps,
+                     hmc_steps=hmc, plain=args.plain, with_cpu=not args.no_cpu,
+                     cpu_min_n=8 if stress else 0)
+    secondary = None
+    if stress and not args.no_secondary:
+        r2 = run_single(args, "realistic", steps=args.steps, warmup=args.warmup,
+                        grad_steps=0 if args.no_grad else args.steps, hmc_steps=0, plain=args.plain,
+                        with_cpu=False)
+        secondary = {"realistic": {k: r2[k] for k in (
+            "value", "ms_per_step", "config", "fine_points_per_s", "plain_evals_per_s", "speedup_vs_plain",
+            "grad_evals_per_s", "ms_per_grad_step", "roofline", "roofline_adjoint") if k in r2}}
+    line = {
+        "metric": "likelihood evals/s and gradient evals/s (params×spaxels/s), batched vs plain",
+        "value": res.pop("value"),
+        "unit": "likelihood evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res.pop("ms_per_step"),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        **res,
+    }
+    if secondary:
+        line["secondary"] = secondary
     print(json.dumps(line), flush=True)
-    grid.close()
 
 
 if __name__ == "__main__":

@@ -215,6 +215,19 @@ int set_launch_shape(gk_grid_t grid, int batch_min, int band_h, int band_w, int 
  * which time this shape alongside their own candidates. */
 int get_launch_shape(gk_grid_t grid, int B, int* band_h, int* band_w, int* steps);
 
+/* Launch shape of the gradient's second pass (the adjoint kernel): bands of
+ * band_h x band_w pixels per workgroup (band_w <= 128, at most 1024 bands)
+ * and `rows` lattice rows per phase (1..16; 0 = chosen from the band width).
+ * GK_EINVAL if the shape does not fit the kernel's limits (80 KiB of LDS).
+ * Not a hot-path call: it may allocate the per-band gradient partials and
+ * then synchronises the device.  For autotuners. */
+int set_adjoint_shape(gk_grid_t grid, int band_h, int band_w, int rows);
+
+/* The adjoint's current launch shape (band_h, band_w, rows), written to host
+ * ints; GK_EINVAL if the grid fits no adjoint shape of this build (then only
+ * the forward calls work on it). */
+int get_adjoint_shape(gk_grid_t grid, int* band_h, int* band_w, int* rows);
+
 /* Message describing the last error returned on the calling thread. */
 const char* last_error(void);
 

@@ -29,7 +29,7 @@ GK_PSF_MAPS, GK_PSF_LUMINOSITY = 0, 1
 
 EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",
            "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "loglike_joint", "get_launch_shape", "ml_from_colour",
-           "brightness_errors", "last_error")
+           "brightness_errors", "set_adjoint_shape", "get_adjoint_shape", "last_error")
 
 
 class GalkinError(RuntimeError):
@@ -67,6 +67,8 @@ def _load() -> ctypes.CDLL:
     lib.loglike_multi.argtypes = [vp, i, vp, vp, i, vp, vp, vp]
     lib.loglike_joint.argtypes = [vp, i, vp, i, i, vp, vp, vp]
     lib.get_launch_shape.argtypes = [vp, i, vp, vp, vp]
+    lib.set_adjoint_shape.argtypes = [vp, i, i, i]
+    lib.get_adjoint_shape.argtypes = [vp, vp, vp, vp]
     lib.ml_from_colour.argtypes = [vp, vp, vp, vp, i, d, d, d, vp, vp, vp]
     lib.brightness_errors.argtypes = [vp, i, d, d, vp, vp]
     lib.last_error.restype = ctypes.c_char_p
@@ -282,6 +284,17 @@ def get_launch_shape(handle: int, B: int):
     return h.value, w.value, st.value
 
 
+def set_adjoint_shape(handle: int, band_h: int, band_w: int, rows: int = 0) -> None:
+    _check(_lib.set_adjoint_shape(handle, int(band_h), int(band_w), int(rows)))
+
+
+def get_adjoint_shape(handle: int):
+    """(band_h, band_w, rows) of the gradient's adjoint launch."""
+    h, w, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lib.get_adjoint_shape(handle, ctypes.byref(h), ctypes.byref(w), ctypes.byref(st)))
+    return h.value, w.value, st.value
+
+
 def last_error() -> str:
     return _lib.last_error().decode()
 
@@ -322,6 +335,12 @@ class Grid:
 
     def set_launch_shape(self, batch_min, band_h, band_w, steps=0):
         set_launch_shape(self.handle, batch_min, band_h, band_w, steps)
+
+    def set_adjoint_shape(self, band_h, band_w, rows=0):
+        set_adjoint_shape(self.handle, band_h, band_w, rows)
+
+    def adjoint_shape(self):
+        return get_adjoint_shape(self.handle)
 
     def launch_shape(self, B):
         return get_launch_shape(self.handle, B)

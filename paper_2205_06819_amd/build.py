@@ -4,10 +4,16 @@
 
 (run by path: importing the package would load the library being rebuilt).
 
-Compiles paper_2205_06819_amd/csrc/galkin.hip with hipcc into
-paper_2205_06819_amd/libgalkin.so.  Packed FP32 instructions are disabled
-(``-packed-fp32-ops``); the host pass warns that it does not know that
-target feature, which is harmless.
+Compiles the translation units under paper_2205_06819_amd/csrc with hipcc in
+parallel and links them into paper_2205_06819_amd/libgalkin.so:
+
+* galkin.hip      host side of the C ABI, HMC update and data-preparation kernels;
+* fwd_inst.hip    the single-grid forward kernel, once per (mode, PSF mode) pair;
+* multi_inst.hip  the many-grid forward kernel, once per PSF mode;
+* adj.hip         the adjoint kernel, once per PSF mode.
+
+Packed FP32 instructions are disabled (``-packed-fp32-ops``); the host pass
+warns that it does not know that target feature, which is harmless.
 """
 from __future__ import annotations
 
@@ -15,12 +21,20 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgalkin.so")
 ARCH = os.environ.get("GALKIN_ARCH", "gfx950")
+
+# (object name, source, extra defines)
+UNITS = [("galkin", "galkin.hip", [])]
+UNITS += [(f"fwd_m{m}_l{l}", "fwd_inst.hip", [f"-DGK_MODE={m}", f"-DGK_LW={l}"]) for m in (0, 1, 2) for l in (0, 1)]
+UNITS += [(f"multi_l{l}", "multi_inst.hip", [f"-DGK_LW={l}"]) for l in (0, 1)]
+UNITS += [(f"adj_l{l}", "adj.hip", [f"-DGK_LW={l}"]) for l in (0, 1)]
 
 
 def hipcc() -> str:
@@ -30,26 +44,44 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (set HIPCC)")
 
 
-def build(verbose: bool = False) -> str:
-    src = os.path.join(CSRC, "galkin.hip")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-O3", "-std=c++17", "-shared", "-fPIC", f"--offload-arch={ARCH}",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument", "-Wno-unused-result",
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           src, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), file=sys.stderr)
+def _flags():
+    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-command-line-argument", "-Wno-unused-result",
+            "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{res.stderr[-8000:]}")
     errs = [l for l in res.stderr.splitlines() if ": error:" in l]
-    if errs:
-        raise RuntimeError("\n".join(errs))
-    os.replace(tmp, LIB)
+    if res.returncode != 0 or errs:
+        raise RuntimeError(f"{' '.join(cmd[:2])} ... failed ({res.returncode}):\n{res.stderr[-8000:]}")
+    return res
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    cc = hipcc()
+    jobs = jobs or max(1, min(len(UNITS), os.cpu_count() or 1, 16))
+    with tempfile.TemporaryDirectory(prefix="galkin_build_") as tmp:
+        cmds = []
+        for name, src, defs in UNITS:
+            obj = os.path.join(tmp, name + ".o")
+            cmds.append([cc, *_flags(), *defs, "-c", os.path.join(CSRC, src), "-o", obj])
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), file=sys.stderr)
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            list(ex.map(_run, cmds))
+        out = LIB + ".tmp"
+        link = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}",
+                *[os.path.join(tmp, n + ".o") for n, _, _ in UNITS], "-o", out]
+        if verbose:
+            print(" ".join(link), file=sys.stderr)
+        _run(link)
+        os.replace(out, LIB)
     return LIB
 
 
 if __name__ == "__main__":
-    path = build(verbose=True)
+    path = build(verbose="-v" in sys.argv)
     print(path)

@@ -1,0 +1,353 @@
+// Adjoint of the likelihood: d logL / d theta from the forward pass's
+// per-pixel adjoints rbar = d logL / d F (written by the forward kernel in its
+// adjoint-seed mode), compiled once per PSF mode (-DGK_LW=0|1).
+//
+// One workgroup = one parameter vector x one band of pixels.  The band's
+// share of the gradient is the sum, over the band's pixels p and maps m, of
+// rbar_m(p) dF_m(p)/dtheta; F_m(p) averages the model over the lattice points
+// of p's 3-sigma stencil (Sec. 3.1, PSF equation), so the share needs the
+// adjoint of every lattice point of the band's padded lattice,
+//   fbar(x, r) = (1/W) sum_p rbar(p) g(|x - x_p|) g(|r - r_p|) [inside the stencil],
+// (the transposed stencil), followed by the reverse point model.  Bands add
+// up exactly to the whole grid (each pixel belongs to one band), so the halo
+// points of neighbouring bands need no exchange.  The lattice is streamed top
+// to bottom in phases of R lattice rows (any R, independent of s):
+//
+//   ring       the pixel rows of rbar the phase reaches (a ring of
+//              D + 1 + ceil((R - 1) / s) rows, new rows loaded per phase);
+//   vertical   per (lattice row, pixel column): running sums S_l of
+//              g(|b|) rbar over the pixel rows in reach, grouped by the
+//              stencil half-width A(|b|) (largest first);
+//   horizontal per lattice point: fbar = (1/W) sum over the D + 1 pixel
+//              columns in reach of g(|t|) S_l(t), l(t) = groups with A >= |t|
+//              (both tables are uniform per row phase and column phase and are
+//              built on the host), then the reverse point model into 27 FP32
+//              adjoints of the per-theta constants.
+//
+// The constant adjoints are summed in FP64 (waves, then bands in order, by
+// the last workgroup of the vector), and the chain rule to theta runs once.
+#include "gk_fwd.h"
+
+#ifndef GK_LW
+#error "compile with -DGK_LW=<0|1>"
+#endif
+
+namespace gk {
+
+// Chain rule from the adjoints of the FP32 constants of make_tc to the
+// parameters (FP64), then writes the gradient row (zeros past P), or adds it
+// to the row (accum; the padding columns are left alone).
+__device__ inline void chain_rule(const double* th, const GridGeom& g, const double* cb, double* out,
+                                  int stride, int accum) {
+    const double d2r = PI / 180.0, LN10 = 2.302585092994046;
+    double gr[32];
+    for (int k = 0; k < 32; ++k) gr[k] = 0.0;
+    const double pa = th[2] * d2r, inc = th[3] * d2r;
+    double spa, cpa, si, ci;
+    sincos(pa, &spa, &cpa);
+    sincos(inc, &si, &ci);
+    const double pks = g.pk / g.s;
+    gr[0] = cb[C_UF] * g.s * g.fscale;
+    gr[1] = cb[C_VF] * g.s * g.fscale;
+    gr[2] = (cb[C_CA] * (-pks * spa) + cb[C_SA] * (pks * cpa)) * d2r;
+    gr[3] = cb[C_SEC2I] * 2.0 * si / (ci * ci * ci) * d2r;
+    int k = 4;
+    if (g.bulge) {
+        const double Mb = exp10(th[k]), Rb = th[k + 1], ML = th[k + 2];
+        const double fa = g.bulge == 2 ? 1.0 : 2.0 * PI, fc = g.bulge == 2 ? 4.0 * PI : 12.0 * PI;
+        const double Ab = 1.0e-6 * Mb / (fa * Rb * Rb * ML);
+        const double Cb = 1.0e-6 * G_KPC * Mb * Mb / (fc * Rb * Rb * Rb * ML);
+        const double GMb = G_KPC * Mb;
+        gr[k] = (cb[C_AB] * Ab + 2.0 * cb[C_CB] * Cb + cb[C_GMB] * GMb) * LN10;
+        gr[k + 1] = -cb[C_INVRB] / (Rb * Rb) - 2.0 * cb[C_AB] * Ab / Rb - 3.0 * cb[C_CB] * Cb / Rb + cb[C_RB];
+        gr[k + 2] = -cb[C_AB] * Ab / ML - cb[C_CB] * Cb / ML + cb[C_MLB];
+        k += 3;
+    }
+    for (int j = 0; j < g.ndisc; ++j) {
+        const int o = C_D0 + 7 * j;
+        const double Md = exp10(th[k]), Rd = th[k + 1], ML = th[k + 2], kk = th[k + 3];
+        const double nl2Rd = -1.4426950408889634 / Rd;
+        const double Ad = 1.0e-6 * Md / (2.0 * PI * Rd * Rd * ci * ML);
+        const double inv2Rd = 0.5 / Rd;
+        const double Kd = 2.0 * G_KPC * Md / Rd;
+        gr[k] = (cb[o + 1] * Ad + cb[o + 3] * Kd) * LN10;
+        gr[k + 1] = -(cb[o + 0] * nl2Rd + 2.0 * cb[o + 1] * Ad + cb[o + 2] * inv2Rd + cb[o + 3] * Kd) / Rd;
+        gr[k + 2] = -cb[o + 1] * Ad / ML + cb[o + 6];
+        gr[k + 3] = -cb[o + 4] * si - cb[o + 5] * 2.0 * kk / 3.0;
+        gr[3] += (cb[o + 1] * Ad * si / ci - cb[o + 4] * kk * ci) * d2r;
+        k += 4;
+    }
+    if (g.halo == 2) {
+        const double M200 = exp10(th[k]), conc = th[k + 1];
+        const double r200 = cbrt(3.0 * M200 / (4.0 * PI * 200.0 * g.rho_crit));
+        const double rs = r200 / conc;
+        const double muc = log1p(conc) - conc / (1.0 + conc);
+        const double H0 = 1.0 / rs, H1 = G_KPC * M200 / (rs * muc);
+        const double dmu = conc / ((1.0 + conc) * (1.0 + conc));
+        gr[k] = (-cb[C_H0] * H0 / 3.0 + cb[C_H1] * H1 * 2.0 / 3.0) * LN10;
+        gr[k + 1] = cb[C_H0] / r200 + cb[C_H1] * H1 * (1.0 / conc - dmu / muc);
+        k += 2;
+    } else if (g.halo == 1) {
+        const double H1 = G_KPC * exp10(th[k]);
+        gr[k] = cb[C_H1] * H1 * LN10;
+        gr[k + 1] = cb[C_H0];
+        k += 2;
+    }
+    if (accum)
+        for (int q = 0; q < k; ++q) out[q] += gr[q];
+    else
+        for (int q = 0; q < stride; ++q) out[q] = q < k ? gr[q] : 0.0;
+}
+
+template <int BULGE, int NDISC, int HALO, int LW>
+__global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
+    extern __shared__ __align__(16) float smem[];
+    const int tid = threadIdx.x, BS = blockDim.x;
+    const int band = blockIdx.x % a.nbands;
+    const int b = blockIdx.x / a.nbands;
+    const GridGeom& G = a.geo;
+    const int s = G.s, pad = G.pad, hs = G.hs, D = a.D;
+    const int by = band / a.nbx, bx = band - by * a.nbx;
+    const int j0 = by * a.band_h, j1 = min(G.ny, j0 + a.band_h);
+    const int c0 = bx * a.band_w, c1 = min(G.nx, c0 + a.band_w);
+    const int NR = j1 - j0, NC = c1 - c0;
+    const int NFR = (NR - 1) * s + 2 * pad + 1;
+    const int vlo = j0 * s + hs, ubase = c0 * s + hs;
+    const int RS = a.rows, NLEV = a.nlev, NCP = NC + 2 * D, RB = a.rb, KP2 = a.KP >> 1;
+    const AdjLayout L = adj_layout(a.band_h, a.band_w, s, pad, D, RS, NLEV, RB, a.KP);
+    float* s_tab = smem + L.tab;
+    float4* s_ring = (float4*)(smem + L.ring);      // [RB][NC]
+    float4* s_S = (float4*)(smem + L.S);            // [RS][NCP][NLEV]
+    const int4* s_ht = (const int4*)(smem + L.ht);  // [s][s][KP2]
+    const int2* s_vt = (const int2*)(smem + L.vt);  // [s][DSTRIDE]
+    double* s_red = (double*)(smem + L.red);
+    int* s_lo = (int*)(smem + L.lo);
+    int* s_hi = (int*)(smem + L.hi);
+    int2* s_span = (int2*)(smem + L.span);
+    int* s_aof = (int*)(smem + L.aof);
+    int* s_plo = (int*)(smem + L.plo);
+    int* s_pw = (int*)(smem + L.pw);
+
+    const double* th = a.theta + (size_t)b * a.stride;
+    const TC tc = uniform_tc(make_tc(th, G));
+    if (!tc.valid) {
+        if (band == 0 && !a.accum)
+            for (int q = tid; q < a.stride; q += BS) a.grad[(size_t)b * a.stride + q] = 0.0;
+        return;
+    }
+    // ---- prologue: tables, zeroed ring and S buffer, row spans
+    {
+        const float* tgh = BULGE == 2 ? gk_tab_jgh : gk_tab_gh;
+        for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = tgh[i];
+        for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
+        for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
+        int* ht = (int*)(smem + L.ht);
+        const int* ght = (const int*)a.ht;
+        for (int i = tid; i < s * s * a.KP * 2; i += BS) ht[i] = ght[i];
+        int* vt = (int*)(smem + L.vt);
+        const int* gvt = (const int*)a.vt;
+        for (int i = tid; i < s * DSTRIDE * 2; i += BS) vt[i] = gvt[i];
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int i = tid; i < RB * NC; i += BS) s_ring[i] = z;
+        for (int i = tid; i < RS * NCP * NLEV; i += BS) s_S[i] = z;
+        for (int i = tid; i < NR; i += BS) s_span[i] = a.span[j0 + i];
+        for (int i = tid; i <= pad; i += BS) s_aof[i] = a.aof[i];
+    }
+    __syncthreads();
+    // needed lattice columns of each lattice row: the union of the stencils of
+    // the band's valid pixels (elsewhere every pixel adjoint in reach is zero)
+    for (int r = tid; r < NFR; r += BS) {
+        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
+        const int jhi = min(NR - 1, r / s);
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int jj = jlo; jj <= jhi; ++jj) {
+            int bb = r - jj * s - pad;
+            bb = bb < 0 ? -bb : bb;
+            const int2 sp = s_span[jj];
+            const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
+            if (cl <= ch) {
+                const int A = s_aof[bb];
+                lo = min(lo, cl * s + hs + pad - A);
+                hi = max(hi, ch * s + hs + pad + A);
+            }
+        }
+        s_lo[r] = hi >= lo ? lo - ubase : (1 << 30);
+        s_hi[r] = hi >= lo ? hi - ubase : -(1 << 30);
+    }
+    __syncthreads();
+    const int nph = (NFR + RS - 1) / RS;
+    for (int k = tid; k < nph; k += BS) {
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int r = k * RS; r < min(NFR, (k + 1) * RS); ++r) {
+            lo = min(lo, s_lo[r]);
+            hi = max(hi, s_hi[r]);
+        }
+        s_plo[k] = hi >= lo ? lo : 0;
+        s_pw[k] = hi >= lo ? hi - lo + 1 : 0;
+    }
+    __syncthreads();
+
+    const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
+                 (const float4*)(s_tab + TAB_GH + TAB_PHI)};
+    float ad[NCONST];
+#pragma unroll
+    for (int k = 0; k < NCONST; ++k) ad[k] = 0.0f;
+    const float invW = a.invW;
+    const float inv_s = 1.0f / (float)s;
+    const float inv_nc = 1.0f / (float)NC;
+    const size_t mstr = (size_t)G.ny * G.nx;
+    const float* fb = a.fbar + (size_t)b * 4 * mstr;
+    int loaded = -1;                                // last pixel row put in the ring
+    for (int rA = 0, ph_i = 0; rA < NFR; rA += RS, ++ph_i) {
+        const int nrow = min(RS, NFR - rA);
+        // pixel rows [qlo - D, qhi] are in reach of lattice rows [rA, rA + nrow); ring
+        // slot of pixel row jj: base + jj - (qlo - D), wrapped, base = (qlo - D) mod RB
+        const int qlo = rA / s, qhi = (rA + nrow - 1) / s;
+        const int base = ((qlo - D) % RB + RB) % RB;
+        // ---- the phase's new pixel rows (loaded + 1 .. qhi; zeros past the band)
+        const int nnew = qhi - loaded;
+        for (int p = tid; p < nnew * NC; p += BS) {
+            const int k = (int)(((float)p + 0.5f) * inv_nc), cc = p - k * NC;
+            const int jj = loaded + 1 + k;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (jj < NR) {
+                const size_t pix = (size_t)(j0 + jj) * G.nx + c0 + cc;
+                v = make_float4(fb[pix], fb[mstr + pix], fb[2 * mstr + pix], fb[3 * mstr + pix]);
+            }
+            int slot = base + jj - (qlo - D);
+            slot = slot >= RB ? slot - RB : slot;
+            s_ring[slot * NC + cc] = v;
+        }
+        loaded = qhi;
+        __syncthreads();
+        // ---- vertical pass: group sums per (lattice row, pixel column)
+        for (int p = tid; p < nrow * NC; p += BS) {
+            const int rl = (int)(((float)p + 0.5f) * inv_nc), cc = p - rl * NC;
+            const int r = rA + rl;
+            const int qr = (int)(((float)r + 0.5f) * inv_s), ph = r - qr * s;
+            const int2* vt = s_vt + ph * DSTRIDE;
+            float4* Sp = s_S + ((size_t)rl * NCP + cc + D) * NLEV;
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int off0 = base + qr - qlo + D;       // ring position of pixel row qr, unwrapped
+            for (int n = 0; n <= D; ++n) {
+                const int2 e = vt[n];
+                const int d = e.x & 255;
+                const float w = __int_as_float(e.y);
+                int slot = off0 - d;
+                slot = slot >= RB ? slot - RB : slot;
+                const float4 v = s_ring[slot * NC + cc];
+                acc.x = fmaf(w, v.x, acc.x);
+                acc.y = fmaf(w, v.y, acc.y);
+                acc.z = fmaf(w, v.z, acc.z);
+                acc.w = fmaf(w, v.w, acc.w);
+                if (e.x >> 16) Sp[(e.x >> 8) & 255] = acc;
+            }
+        }
+        __syncthreads();
+        // ---- horizontal gather and reverse point model, flat over the phase's points
+        const int plo = s_plo[ph_i], pw = s_pw[ph_i];
+        const int npts = nrow * pw;
+        const float inv_pw = 1.0f / (float)max(pw, 1);
+        for (int qq = tid; qq < npts; qq += BS) {
+            const int rl = (int)(((float)qq + 0.5f) * inv_pw);
+            const int x = plo + (qq - rl * pw);
+            const int qr = (int)(((float)(rA + rl) + 0.5f) * inv_s), ph = rA + rl - qr * s;
+            const int qx = (int)(((float)x + 0.5f) * inv_s), ix = x - qx * s;
+            const float4* Sb = s_S + ((size_t)rl * NCP + qx + D) * NLEV;
+            const int4* h = s_ht + (ph * s + ix) * KP2;
+            float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int k2 = 0; k2 < KP2; ++k2) {
+                const int4 e = h[k2];
+                const float4 v0 = Sb[e.x], v1 = Sb[e.z];
+                const float w0 = __int_as_float(e.y), w1 = __int_as_float(e.w);
+                f.x = fmaf(w1, v1.x, fmaf(w0, v0.x, f.x));
+                f.y = fmaf(w1, v1.y, fmaf(w0, v0.y, f.y));
+                f.z = fmaf(w1, v1.z, fmaf(w0, v0.z, f.z));
+                f.w = fmaf(w1, v1.w, fmaf(w0, v0.w, f.w));
+            }
+            const int r = rA + rl;
+            const float du = (float)(ubase + x - tc.Ui) - tc.Uf;
+            const float dv = (float)(vlo + r - tc.Vi) - tc.Vf;
+            float4 fo = make_float4(f.x * invW, f.y * invW, f.z * invW, f.w * invW);
+            if (LW) {
+                // the lattice carries (B, B v, B (sigma^2 + v^2), B / <L/M>): map their
+                // adjoints to those of (B, v, sigma, <L/M>) at this point
+                float pB, pV, pS, pL;
+                point_model<BULGE, NDISC, HALO>(tc, T, du, dv, pB, pV, pS, pL);
+                const float il = frcp(pL);
+                fo = make_float4(fo.x + fo.y * pV + fo.z * fmaf(pS, pS, pV * pV) + fo.w * il,
+                                 fmaf(fo.y, pB, 2.0f * fo.z * pB * pV), 2.0f * fo.z * pB * pS,
+                                 -fo.w * pB * il * il);
+            }
+            point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
+        }
+        __syncthreads();
+    }
+
+    // ---- FP64 reduction of the constant adjoints: waves (all constants
+    // stepped together, so the shuffles overlap), then bands in order
+    const int lane = tid & 63, wave = tid >> 6, nw = (BS + 63) >> 6;
+    {
+        double v[NCONST];
+#pragma unroll
+        for (int k = 0; k < NCONST; ++k) v[k] = (double)ad[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+            for (int k = 0; k < NCONST; ++k) v[k] += __shfl_down(v[k], o, 64);
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < NCONST; ++k) s_red[wave * NCONST + k] = v[k];
+    }
+    __syncthreads();
+    double* gp = a.gpart + ((size_t)b * a.nbands + band) * NCONST;
+    if (tid < NCONST) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += s_red[w * NCONST + tid];
+        gp[tid] = t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        bool last = true;
+        if (a.nbands > 1) {
+            const unsigned ticket = __hip_atomic_fetch_add(a.counters + b, 1u, __ATOMIC_ACQ_REL,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            last = ticket == (unsigned)a.nbands - 1;
+        }
+        if (last) {
+            double cb[NCONST];
+            for (int k = 0; k < NCONST; ++k) cb[k] = 0.0;
+            for (int bnd = 0; bnd < a.nbands; ++bnd)
+                for (int k = 0; k < NCONST; ++k)
+                    cb[k] += __hip_atomic_load(a.gpart + ((size_t)b * a.nbands + bnd) * NCONST + k,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            chain_rule(th, G, cb, a.grad + (size_t)b * a.stride, a.stride, a.accum);
+            if (a.nbands > 1) __hip_atomic_store(a.counters + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <int LW>
+hipError_t launch_adj_lw(int bulge, int nd, int halo, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                         const AdjArgs& a) {
+#define GK_ALAUNCH(BU, ND, HA)                                                        \
+    if (bulge == BU && nd == ND && halo == HA) {                                       \
+        hipLaunchKernelGGL((adj_kernel<BU, ND, HA, LW>), grid, block, lds, st, a);    \
+        return hipGetLastError();                                                      \
+    }
+    GK_ALAUNCH(1, 0, 0) GK_ALAUNCH(1, 0, 1) GK_ALAUNCH(1, 0, 2)
+    GK_ALAUNCH(1, 1, 0) GK_ALAUNCH(1, 1, 1) GK_ALAUNCH(1, 1, 2)
+    GK_ALAUNCH(1, 2, 0) GK_ALAUNCH(1, 2, 1) GK_ALAUNCH(1, 2, 2)
+    GK_ALAUNCH(2, 0, 0) GK_ALAUNCH(2, 0, 1) GK_ALAUNCH(2, 0, 2)
+    GK_ALAUNCH(2, 1, 0) GK_ALAUNCH(2, 1, 1) GK_ALAUNCH(2, 1, 2)
+    GK_ALAUNCH(2, 2, 0) GK_ALAUNCH(2, 2, 1) GK_ALAUNCH(2, 2, 2)
+    GK_ALAUNCH(0, 1, 0) GK_ALAUNCH(0, 1, 1) GK_ALAUNCH(0, 1, 2)
+    GK_ALAUNCH(0, 2, 0) GK_ALAUNCH(0, 2, 1) GK_ALAUNCH(0, 2, 2)
+#undef GK_ALAUNCH
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_adj_lw<GK_LW>(int, int, int, dim3, dim3, size_t, hipStream_t, const AdjArgs&);
+
+}  // namespace gk

@@ -1,22 +1,8 @@
-// galkin: HIP implementation (gfx950) of the batched disc-galaxy likelihood.
-//
-// One workgroup evaluates one parameter vector (theta) on one rectangular
-// band of pixels.  It streams the band's padded fine lattice row by row:
-//
-//   model phase   every thread evaluates lattice points of the next chunk
-//                 (paper Sec. 2.1-2.4) into an LDS ring buffer;
-//   stencil phase each (pixel column, map) pair forms the horizontal partial
-//                 sums of the circular Gaussian stencil (Sec. 3.1, PSF
-//                 equation) along each completed lattice row and pushes them,
-//                 weighted by the vertical Gaussian factor, into LDS
-//                 accumulators of the pixel rows that row reaches;
-//   finalize      when the last lattice row of a pixel row is in, that row's
-//                 PSF averages are complete: residuals against the data and
-//                 the FP64 chi^2 (Sec. 2.5.1, likelihood equation).
-//
-// Only lattice points inside the union of the stencils of valid pixels are
-// evaluated.  Per-band FP64 partial chi^2 are combined in band order by the
-// last workgroup of each theta (deterministic, graph-capturable).
+// galkin: host side of the C ABI (include/galkin.h) for gfx950: grid
+// descriptors, stencil tables, data upload, launch shapes, the many-grid work
+// plans, the HMC trajectory and the data-preparation kernels.  The likelihood
+// kernels live in their own translation units (fwd_inst.hip, multi_inst.hip,
+// adj.hip) behind the launch entry points of gk_kern.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,781 +15,9 @@
 #include <vector>
 
 #include "galkin.h"
-#include "gk_device.h"
+#include "gk_kern.h"
 
 namespace gk {
-
-enum { MODE_LOGL = 0, MODE_FBAR = 1, MODE_MAPS = 2 };
-constexpr int MAX_BANDS = 1024;       // per theta
-constexpr int RED_SLOTS = 16;         // waves per workgroup (<= 1024 threads)
-
-struct FwdArgs {
-    GridGeom geo;
-    const float* gw;        // [64] 1-D Gaussian factors exp(-a^2 / 2 (sigma s)^2), zero beyond pad
-    const int* aof;         // [pad + 1] half-width A(|b|) of the stencil at row offset b
-    const int2* tab;        // [s][DSTRIDE] (A(|b|), weight bits g(|b|)) for lattice-row phase ph and
-                            // pixel-row lag d, b = d s + ph - pad; (0, 0) where |b| > pad
-    float invW;             // 1 / sum of the 2-D stencil weights
-    int D;                  // floor(2 pad / s): lag at which a pixel row is complete
-    const float* val;       // data [4][ny][nx]
-    const float* ivar;      // inverse variances [4][ny][nx], 0 = masked
-    const int2* span;       // [ny] first / last column valid in any map
-    const double* logdet;   // sum of ln(2 pi e^2) over valid pixels (device scalar)
-    int band_h, band_w, nbx, nbands;
-    int pstride;            // row stride of partials (>= nbands)
-    int gsub;               // pixel-row steps per model phase (gsub * s <= RS_CAP lattice rows)
-    int xw;                 // row stride of the row buffer (floats)
-    int tpad;               // compile-time tap count used by the stencil (>= pad)
-    const double* theta;
-    int stride;
-    double* logL;
-    float* maps;            // MODE_MAPS output [B][4][ny][nx]
-    float* fbar;            // MODE_FBAR output [B][4][ny][nx]: d logL / d F
-    double* partials;       // [B][pstride]
-    unsigned* counters;     // [B]
-    int accum;              // 1: add the log-likelihood to logL[b] instead of storing it
-    int map_mask;           // bit m set: map m is convolved (maps with no valid pixel are skipped)
-};
-
-constexpr int DMAX = 10;        // largest lag D = floor(2 pad / s) supported
-constexpr int DSTRIDE = DMAX + 1;
-constexpr int RS_CAP = 16;      // lattice rows per model phase
-constexpr int GSUB_CAP = 4;     // pixel-row steps per model phase
-
-struct Layout {                 // LDS carve-up, identical on host and device
-    int tab, rows, red, rows_lo, rows_start, stage, fin, total_bytes;
-};
-
-__host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
-
-// nfin: floats of the per-step exchange buffer of the luminosity-weighted
-// mode (0 otherwise)
-__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int band_h, int nfin) {
-    Layout L;
-    int off = 0;                                   // in 4-byte words
-    L.rows = off;       off += rows * 4 * xw;
-    off = (off + 3) & ~3;
-    L.red = off;        off += 2 * RED_SLOTS;      // doubles
-    L.rows_lo = off;    off += nfrm;
-    L.rows_start = off; off += nfrm + 1 + RS_CAP;  // padded: phase lookups read ahead
-    off = (off + 1) & ~1;
-    L.stage = off;      off += 2 * band_h + 32;    // row spans and stencil half-widths
-    L.fin = off;        off += nfin;
-    // the tables last, at a launch-dependent offset: a table lookup is then one
-    // base add and four reads with immediate offsets
-    off = (off + 3) & ~3;
-    L.tab = off;        off += TAB_ALL;
-    L.total_bytes = 4 * off;
-    return L;
-}
-
-// Block-wide exclusive scan of n ints in place (n small); returns the total.
-__device__ inline int block_exclusive_scan(int* a, int n, int* scratch /*RED_SLOTS ints*/) {
-    const int tid = threadIdx.x, BS = blockDim.x;
-    const int per = (n + BS - 1) / BS;
-    const int lo = min(n, tid * per), hi = min(n, lo + per);
-    int sum = 0;
-    for (int i = lo; i < hi; ++i) sum += a[i];
-    const int lane = tid & 63, wave = tid >> 6;
-    int x = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) scratch[wave] = x;
-    __syncthreads();
-    int wbase = 0;
-    const int nw = (BS + 63) >> 6;
-    for (int w = 0; w < wave; ++w) wbase += scratch[w];
-    int total = 0;
-    for (int w = 0; w < nw; ++w) total += scratch[w];
-    int run = wbase + x - sum;                      // exclusive prefix of this thread
-    for (int i = lo; i < hi; ++i) {
-        const int v = a[i];
-        a[i] = run;
-        run += v;
-    }
-    __syncthreads();
-    return total;
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
-}
-
-typedef const __attribute__((address_space(4))) int* const_int_ptr;
-
-// One pixel-row step of the separable stencil for one (map, pixel column).
-// The step's s lattice rows (phases) each give horizontal partial sums
-// H_0..H_PAD at the pixel centre from one batch of LDS loads; the pixel row
-// at lag d (d steps back) takes weight g(|b|) times H_A(|b|), b = d s + ph - pad.
-// acc[d] holds the running PSF sum of the pixel row d steps back; it is
-// shifted by one each step, so acc[D] is complete after this call.
-template <int PAD>
-__device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rstride, int s,
-                                            const float* __restrict__ gw, const int2* __restrict__ tab,
-                                            float (&acc)[DMAX + 1]) {
-    float g[PAD + 1];
-#pragma unroll
-    for (int k = 0; k <= PAD; ++k) g[k] = gw[k];
-    float con[DMAX + 1];
-#pragma unroll
-    for (int d = 0; d <= DMAX; ++d) con[d] = 0.0f;
-    for (int ph = 0; ph < s; ++ph) {
-        const float* L = L0 + ph * rstride;
-        float H[PAD + 1];
-        H[0] = g[0] * L[0];
-#pragma unroll
-        for (int k = 1; k <= PAD; ++k) H[k] = fmaf(g[k], L[-k] + L[k], H[k - 1]);
-        // table entries through the constant address space: scalar loads; lags
-        // beyond D have weight 0, so the loop has a fixed trip count
-        const_int_ptr t = (const_int_ptr)tab + 2 * ph * DSTRIDE;
-#pragma unroll
-        for (int d = 0; d <= DMAX; ++d) {
-            const int A = t[2 * d];
-            const float w = __int_as_float(t[2 * d + 1]);
-            con[d] = fmaf(w, H[A], con[d]);
-        }
-    }
-#pragma unroll
-    for (int d = DMAX; d >= 1; --d) acc[d] = acc[d - 1] + con[d];
-    acc[0] = con[0];
-}
-
-// One parameter vector (row b) on one band of one grid.  load_tables = false
-// when the caller already staged the special-function tables in LDS.  LW = 1:
-// the PSF averages luminosity-weighted moments (a compile-time switch, so the
-// map-averaging instantiations do not carry its registers).
-template <int BULGE, int NDISC, int HALO, int MODE, int LW>
-__device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const int band, float* smem,
-                                         const bool load_tables) {
-    const int tid = threadIdx.x, BS = blockDim.x;
-    const GridGeom& G = a.geo;
-    const int s = G.s, pad = G.pad, hs = G.hs;
-    const int by = band / a.nbx, bx = band - by * a.nbx;
-    const int j0 = by * a.band_h, j1 = min(G.ny, j0 + a.band_h);
-    const int c0 = bx * a.band_w, c1 = min(G.nx, c0 + a.band_w);
-    const int NR = j1 - j0, NC = c1 - c0;
-    const int NFR = (NR - 1) * s + 2 * pad + 1;
-    const int vlo = j0 * s + hs;                    // lattice row of local row 0
-    const int ubase = c0 * s + hs;                  // lattice column of local column 0
-    const int nfrm = nfr_max(a.band_h, s, pad);
-    const int RS = a.gsub * s;
-    const Layout L = make_layout(RS, a.xw, nfrm, a.band_h, LW ? 8 * a.gsub * a.band_w : 0);
-    float* s_tab = smem + L.tab;
-    float* s_rows = smem + L.rows;
-    double* s_red = (double*)(smem + L.red);
-    int* s_lo = (int*)(smem + L.rows_lo);
-    int* s_start = (int*)(smem + L.rows_start);
-    float* s_fin = smem + L.fin;                    // [2][gsub][4][band_w] (luminosity-weighted mode)
-    const int XW = a.xw;
-    const int D = a.D;
-
-    // --- parameters of this theta (FP64 -> FP32 constants, wave-uniform)
-    const TC tc = uniform_tc(make_tc(a.theta + (size_t)b * a.stride, G));
-    if (!tc.valid) {
-        if (MODE == MODE_MAPS) {
-            const float qnan = __int_as_float(0x7fc00000);
-            for (int p = tid; p < 4 * NR * NC; p += BS) {
-                const int m = p / (NR * NC), rem = p - m * NR * NC, jj = rem / NC, c = rem - jj * NC;
-                a.maps[(size_t)b * 4 * G.ny * G.nx + ((size_t)m * G.ny + j0 + jj) * G.nx + c0 + c] = qnan;
-            }
-        } else if (band == 0 && tid == 0) {
-            a.logL[b] = -INFINITY;
-        }
-        return;
-    }
-
-    // --- prologue: tables, zeroed row buffer, row spans
-    if (load_tables) {
-        const float* tgh = BULGE == 2 ? gk_tab_jgh : gk_tab_gh;     // one bulge kind per grid
-        for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = tgh[i];
-        for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
-        for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
-    }
-    for (int i = tid; i < RS * 4 * XW; i += BS) s_rows[i] = 0.0f;
-    // row spans of the band and stencil half-widths, staged for the span pass
-    int2* s_span = (int2*)(smem + L.stage);
-    int* s_aof = (int*)(s_span + a.band_h);
-    for (int i = tid; i < NR; i += BS) s_span[i] = MODE != MODE_MAPS ? a.span[j0 + i] : make_int2(c0, c1 - 1);
-    for (int i = tid; i <= pad; i += BS) s_aof[i] = a.aof[i];
-    __syncthreads();
-    for (int r = tid; r < NFR; r += BS) {
-        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;   // ceil((r - 2 pad) / s)
-        const int jhi = min(NR - 1, r / s);
-        int lo = 1 << 30, hi = -(1 << 30);
-        for (int jj = jlo; jj <= jhi; ++jj) {
-            int bb = r - jj * s - pad;
-            bb = bb < 0 ? -bb : bb;
-            const int2 sp = s_span[jj];
-            const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
-            if (cl <= ch) {
-                const int A = s_aof[bb];
-                lo = min(lo, cl * s + hs + pad - A);
-                hi = max(hi, ch * s + hs + pad + A);
-            }
-        }
-        s_lo[r] = hi >= lo ? lo - ubase : (1 << 30);  // local needed columns of lattice row r
-        s_start[r] = hi >= lo ? hi - ubase : -(1 << 30);
-    }
-    __syncthreads();
-    // one column range per model phase: the union of its lattice rows' ranges
-    // (about 3 % more points than row by row, and no per-point row search)
-    const int RSs = a.gsub * s;
-    const int nph = (NFR + RSs - 1) / RSs;
-    int* s_plo = (int*)(smem + L.stage);                // reuses the staging area
-    int* s_pw = s_plo + nph;
-    __syncthreads();
-    for (int k = tid; k < nph; k += BS) {
-        int lo = 1 << 30, hi = -(1 << 30);
-        for (int r = k * RSs; r < min(NFR, (k + 1) * RSs); ++r) {
-            lo = min(lo, s_lo[r]);
-            hi = max(hi, s_start[r]);
-        }
-        s_plo[k] = hi >= lo ? lo : 0;
-        s_pw[k] = hi >= lo ? hi - lo + 1 : 0;
-    }
-    __syncthreads();
-
-    const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
-                 (const float4*)(s_tab + TAB_GH + TAB_PHI)};
-    const float invW = a.invW;
-    double chi2 = 0.0;
-    const size_t mapoff = (size_t)b * 4 * G.ny * G.nx;
-    // one (map, pixel column) pair per thread: blockDim >= 4 * band_w; the
-    // threads beyond 4 NC run the same code on a clamped pair and store nothing,
-    // which keeps the stencil phase free of divergent control flow
-    const bool pact = tid < 4 * NC;
-    const int tcl = pact ? tid : 4 * NC - 1;
-    const int pm = tcl / NC, pc = tcl - (tcl / NC) * NC;
-    float acc[DMAX + 1];
-#pragma unroll
-    for (int d = 0; d <= DMAX; ++d) acc[d] = 0.0f;
-    const int Q = NR + D;                           // pixel-row steps
-
-    for (int q0 = 0; q0 < Q; q0 += a.gsub) {
-        // ---- lattice rows [rA, rA + nrow) of this phase, columns [plo, plo + pw)
-        const int rA = q0 * s;
-        const int nrow = max(0, min(RS, NFR - rA));
-        const int ph = q0 / a.gsub;
-        const int plo = uni(s_plo[ph]), pw = uni(s_pw[ph]);
-        const int npts = nrow * pw;
-        const float inv_pw = 1.0f / (float)max(pw, 1);
-        // ---- data of the pixel rows completed in this phase (prefetched)
-        float pv[GSUB_CAP], pi[GSUB_CAP];
-        if (MODE != MODE_MAPS) {
-#pragma unroll
-            for (int k = 0; k < GSUB_CAP; ++k) {
-                if (k >= a.gsub) break;
-                const int jj = q0 + k - D;
-                const bool ok = jj >= 0 && jj < NR;
-                const size_t pix = ((size_t)pm * G.ny + j0 + (ok ? jj : 0)) * G.nx + c0 + pc;
-                const float vv = a.val[pix], ii = a.ivar[pix];
-                pv[k] = vv;
-                pi[k] = (ok && pact) ? ii : 0.0f;
-            }
-        }
-        // ---- model phase: the phase's lattice points, flat over its rows
-        for (int q = tid; q < npts; q += BS) {
-            const int lr = (int)(((float)q + 0.5f) * inv_pw);
-            const int r = rA + lr;
-            const int x = plo + (q - lr * pw);                   // local column
-            const int u = ubase + x;
-            const int v = vlo + r;
-            const float du = (float)(u - tc.Ui) - tc.Uf;
-            const float dv = (float)(v - tc.Vi) - tc.Vf;
-            float fB, fV, fS, fL;
-            point_model<BULGE, NDISC, HALO>(tc, T, du, dv, fB, fV, fS, fL);
-            float* row = s_rows + lr * 4 * XW + x;
-            if (LW) {         // light, first and second velocity moments, mass
-                row[0] = fB;
-                row[XW] = fB * fV;
-                row[2 * XW] = fB * fmaf(fS, fS, fV * fV);
-                row[3 * XW] = fB * frcp(fL);
-            } else {
-                row[0] = fB;
-                row[XW] = fV;
-                row[2 * XW] = fS;
-                row[3 * XW] = fL;
-            }
-        }
-        __syncthreads();
-        // ---- stencil phase: per (map, column) pair, in registers
-        {
-#pragma unroll
-            for (int k = 0; k < GSUB_CAP; ++k) {
-                if (k >= a.gsub) break;
-                const int q = q0 + k;
-                if (q >= Q) break;
-                const float* L0 = s_rows + (k * s) * 4 * XW + pm * XW + pc * s + pad;
-#define GK_SUB(PADV) stencil_sub<PADV>(L0, 4 * XW, s, a.gw, a.tab, acc)
-                if ((a.map_mask >> pm) & 1) {       // maps without valid pixels stay zero
-                    switch (a.tpad) {
-                        case 4: GK_SUB(4); break;
-                        case 6: GK_SUB(6); break;
-                        case 9: GK_SUB(9); break;
-                        case 12: GK_SUB(12); break;
-                        case 16: GK_SUB(16); break;
-                        case 20: GK_SUB(20); break;
-                        default: GK_SUB(25); break;
-                    }
-                }
-#undef GK_SUB
-                const int jj = q - D;                   // pixel row completed by this step
-                if (jj >= 0 && LW) {
-                    if (pact) s_fin[(k * 4 + pm) * a.band_w + pc] = acc[D] * invW;
-                } else if (jj >= 0) {
-                    const float F = acc[D] * invW;
-                    const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
-                    if (MODE == MODE_MAPS) {
-                        if (pact) a.maps[mapoff + pix] = (pm == 3) ? 1.0f / F : F;
-                    } else {
-                        const float iv = pi[k];
-                        float gbar = 0.0f;
-                        if (iv > 0.0f) {
-                            const float Fm = (pm == 3) ? 1.0f / F : F;
-                            const float res = Fm - pv[k];
-                            chi2 += (double)res * (double)res * (double)iv;
-                            // d logL / dF: -iv res, and for M/L = 1/F: +iv res / F^2
-                            gbar = (pm == 3) ? iv * res * Fm * Fm : -iv * res;
-                        }
-                        if (MODE == MODE_FBAR && pact) a.fbar[mapoff + pix] = gbar;
-                    }
-                }
-            }
-        }
-        if (LW) {
-            // luminosity-weighted moments: every pixel's four PSF moments are in
-            // s_fin; each (map, column) thread forms its own observable from them
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < GSUB_CAP; ++k) {
-                if (k >= a.gsub) break;
-                const int jj = q0 + k - D;
-                if (jj < 0 || q0 + k >= Q) continue;
-                const float* fk = s_fin + k * 4 * a.band_w + pc;
-                const float F0 = fk[0], F1 = fk[a.band_w], F2 = fk[2 * a.band_w], F3 = fk[3 * a.band_w];
-                const float i0 = frcp(F0);
-                const float v = F1 * i0;
-                const float s2 = fmaf(F2, i0, -v * v);
-                const float sg = s2 > 0.0f ? fsqrt(s2) : 0.0f;
-                const float obs = pm == 0 ? F0 : pm == 1 ? v : pm == 2 ? sg : F3 * i0;   // B, v, sigma, M/L
-                const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
-                if (MODE == MODE_MAPS) {
-                    if (pact) a.maps[mapoff + pix] = obs;
-                } else {
-                    const float iv = pi[k];
-                    float ob = 0.0f;                    // d logL / d observable
-                    if (iv > 0.0f) {
-                        const float res = obs - pv[k];
-                        chi2 += (double)res * (double)res * (double)iv;
-                        ob = -iv * res;
-                    }
-                    // the clamped threads share an active thread's slot: only the owner writes
-                    if (MODE == MODE_FBAR && pact) s_fin[(4 * a.gsub + k * 4 + pm) * a.band_w + pc] = ob;
-                }
-            }
-            if (MODE == MODE_FBAR) {
-                // d logL / d F_m through v = F1/F0, sigma = sqrt(F2/F0 - v^2), M/L = F3/F0
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < GSUB_CAP; ++k) {
-                    if (k >= a.gsub) break;
-                    const int jj = q0 + k - D;
-                    if (jj < 0 || q0 + k >= Q) continue;
-                    const float* fk = s_fin + k * 4 * a.band_w + pc;
-                    const float* ok_ = s_fin + (4 * a.gsub + k * 4) * a.band_w + pc;
-                    const float F0 = fk[0], F1 = fk[a.band_w], F2 = fk[2 * a.band_w], F3 = fk[3 * a.band_w];
-                    const float o0 = ok_[0], o1 = ok_[a.band_w], o2 = ok_[2 * a.band_w], o3 = ok_[3 * a.band_w];
-                    const float i0 = frcp(F0);
-                    const float v = F1 * i0;
-                    const float s2 = fmaf(F2, i0, -v * v);
-                    const float sg = s2 > 0.0f ? fsqrt(s2) : 0.0f;
-                    const float hs2 = sg > 0.0f ? 0.5f * frcp(sg) : 0.0f;          // d sigma / d s2
-                    // s2 = F2/F0 - F1^2/F0^2
-                    const float ds2_0 = (-F2 + 2.0f * F1 * v) * i0 * i0;
-                    const float ds2_1 = -2.0f * v * i0;
-                    const float ds2_2 = i0;
-                    float gbar;
-                    if (pm == 0)
-                        gbar = o0 - o1 * v * i0 + o2 * hs2 * ds2_0 - o3 * F3 * i0 * i0;
-                    else if (pm == 1)
-                        gbar = o1 * i0 + o2 * hs2 * ds2_1;
-                    else if (pm == 2)
-                        gbar = o2 * hs2 * ds2_2;
-                    else
-                        gbar = o3 * i0;
-                    // a pixel with no valid map (outside every map's column span the
-                    // lattice is not evaluated, F0 may be 0) has a zero adjoint
-                    const bool used = (o0 != 0.0f) | (o1 != 0.0f) | (o2 != 0.0f) | (o3 != 0.0f);
-                    gbar = used ? gbar : 0.0f;
-                    const size_t pix = ((size_t)pm * G.ny + j0 + jj) * G.nx + c0 + pc;
-                    if (pact) a.fbar[mapoff + pix] = gbar;
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    if (MODE == MODE_MAPS) return;
-    // ---- FP64 chi^2: wave sums, then waves in order, then bands in order
-    chi2 = wave_sum(chi2);
-    const int lane = tid & 63, wave = tid >> 6;
-    if (lane == 0) s_red[wave] = chi2;
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-        for (int w = 0; w < (BS + 63) / 64; ++w) t += s_red[w];
-        if (a.nbands == 1) {
-            const double v = -0.5 * (t + *a.logdet);
-            a.logL[b] = a.accum ? a.logL[b] + v : v;
-        } else {
-            a.partials[(size_t)b * a.pstride + band] = t;
-            const unsigned ticket = __hip_atomic_fetch_add(a.counters + b, 1u, __ATOMIC_ACQ_REL,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-            if (ticket == (unsigned)a.nbands - 1) {
-                double sum = 0.0;
-                for (int k = 0; k < a.nbands; ++k)
-                    sum += __hip_atomic_load(a.partials + (size_t)b * a.pstride + k, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-                const double v = -0.5 * (sum + *a.logdet);
-                a.logL[b] = a.accum ? a.logL[b] + v : v;
-                __hip_atomic_store(a.counters + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
-}
-
-template <int BULGE, int NDISC, int HALO, int MODE, int LW>
-__global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
-    extern __shared__ __align__(16) float smem[];
-    fwd_band<BULGE, NDISC, HALO, MODE, LW>(a, blockIdx.x / a.nbands, blockIdx.x % a.nbands, smem, true);
-}
-
-// ============================================================================
-// many grids in one launch: workgroup i takes work item i (grid, parameter row
-// within the grid, band, first row of the grid in the batch); the host orders
-// the items by decreasing cost, so the dispatcher hands out the longest items
-// first and the short ones fill the tail.  (A persistent loop over an atomic
-// queue kept loop-invariant state live across items: 206 instead of 125 VGPRs,
-// half the occupancy, and slower overall.)
-// ============================================================================
-typedef const __attribute__((address_space(4))) int* const_word_ptr;
-
-constexpr int MULTI_BS = 256;   // threads per workgroup of the many-grid launch
-
-template <int LW>
-__global__ void __launch_bounds__(MULTI_BS) multi_kernel(const FwdArgs* __restrict__ grids,
-                                                         const int4* __restrict__ items,
-                                                         const double* theta, int stride, double* logL) {
-    extern __shared__ __align__(16) float smem[];
-    const_word_ptr iw = (const_word_ptr)(items) + 4 * blockIdx.x;
-    const int g = iw[0], row = iw[1], band = iw[2], off = iw[3];
-    FwdArgs a = grids[g];
-    a.theta = theta + (size_t)off * stride;   // this grid's rows start at row off
-    a.stride = stride;
-    a.logL = logL + off;
-    const int comp = a.geo.bulge * 100 + a.geo.ndisc * 10 + a.geo.halo;
-    switch (comp) {
-#define GK_MCASE(BU, ND, HA)                                                                   \
-    case BU * 100 + ND * 10 + HA:                                                              \
-        fwd_band<BU, ND, HA, MODE_LOGL, LW>(a, row, band, smem, true);                          \
-        break;
-        GK_MCASE(1, 0, 0) GK_MCASE(1, 0, 1) GK_MCASE(1, 0, 2)
-        GK_MCASE(1, 1, 0) GK_MCASE(1, 1, 1) GK_MCASE(1, 1, 2)
-        GK_MCASE(1, 2, 0) GK_MCASE(1, 2, 1) GK_MCASE(1, 2, 2)
-        GK_MCASE(2, 0, 0) GK_MCASE(2, 0, 1) GK_MCASE(2, 0, 2)
-        GK_MCASE(2, 1, 0) GK_MCASE(2, 1, 1) GK_MCASE(2, 1, 2)
-        GK_MCASE(2, 2, 0) GK_MCASE(2, 2, 1) GK_MCASE(2, 2, 2)
-        GK_MCASE(0, 1, 0) GK_MCASE(0, 1, 1) GK_MCASE(0, 1, 2)
-        GK_MCASE(0, 2, 0) GK_MCASE(0, 2, 1) GK_MCASE(0, 2, 2)
-#undef GK_MCASE
-        default: break;
-    }
-}
-
-// ============================================================================
-// adjoint: d logL / d theta
-// ============================================================================
-constexpr int MAX_BANDS_ADJ = 64;
-
-struct AdjArgs {
-    GridGeom geo;
-    const float* gw;        // [64] 1-D Gaussian factors
-    const int* aof;         // [pad + 1] stencil half-widths
-    float invW;
-    int D;                  // pixel-row lags of the stencil, floor(2 pad / s)
-    const int2* span;       // [ny] valid column spans
-    int band_h, band_w, nbx, nbands;
-    const double* theta;
-    int stride;
-    const float* fbar;      // [B][4][ny][nx] d logL / d F from the forward pass
-    double* gpart;          // [B][nbands][NCONST] per-band constant adjoints
-    unsigned* counters;     // [B], zero on entry, reset by the last band
-    double* grad;           // [B][stride]
-    int accum;              // 1: add the gradient to grad[b] instead of storing it
-};
-
-__host__ __device__ inline int adj_lds_bytes(int band_h, int band_w, int s, int pad) {
-    const int nfrm = nfr_max(band_h, s, pad);
-    return 4 * (TAB_ALL + 4 * band_h * band_w + 64 + 2 * nfrm + 1 + RED_SLOTS * 2 * NCONST + 64 + 2 * band_h +
-                32);
-}
-
-__device__ inline int floor_div(int n, int d) { return n >= 0 ? n / d : -((-n + d - 1) / d); }
-
-// Chain rule from the adjoints of the FP32 constants of make_tc to the
-// parameters (FP64), then writes the gradient row (zeros past P), or adds it
-// to the row (accum; the padding columns are left alone).
-__device__ inline void chain_rule(const double* th, const GridGeom& g, const double* cb, double* out,
-                                  int stride, int accum) {
-    const double d2r = PI / 180.0, LN10 = 2.302585092994046;
-    double gr[32];
-    for (int k = 0; k < 32; ++k) gr[k] = 0.0;
-    const double pa = th[2] * d2r, inc = th[3] * d2r;
-    double spa, cpa, si, ci;
-    sincos(pa, &spa, &cpa);
-    sincos(inc, &si, &ci);
-    const double pks = g.pk / g.s;
-    gr[0] = cb[C_UF] * g.s * g.fscale;
-    gr[1] = cb[C_VF] * g.s * g.fscale;
-    gr[2] = (cb[C_CA] * (-pks * spa) + cb[C_SA] * (pks * cpa)) * d2r;
-    gr[3] = cb[C_SEC2I] * 2.0 * si / (ci * ci * ci) * d2r;
-    int k = 4;
-    if (g.bulge) {
-        const double Mb = exp10(th[k]), Rb = th[k + 1], ML = th[k + 2];
-        const double fa = g.bulge == 2 ? 1.0 : 2.0 * PI, fc = g.bulge == 2 ? 4.0 * PI : 12.0 * PI;
-        const double Ab = 1.0e-6 * Mb / (fa * Rb * Rb * ML);
-        const double Cb = 1.0e-6 * G_KPC * Mb * Mb / (fc * Rb * Rb * Rb * ML);
-        const double GMb = G_KPC * Mb;
-        gr[k] = (cb[C_AB] * Ab + 2.0 * cb[C_CB] * Cb + cb[C_GMB] * GMb) * LN10;
-        gr[k + 1] = -cb[C_INVRB] / (Rb * Rb) - 2.0 * cb[C_AB] * Ab / Rb - 3.0 * cb[C_CB] * Cb / Rb + cb[C_RB];
-        gr[k + 2] = -cb[C_AB] * Ab / ML - cb[C_CB] * Cb / ML + cb[C_MLB];
-        k += 3;
-    }
-    for (int j = 0; j < g.ndisc; ++j) {
-        const int o = C_D0 + 7 * j;
-        const double Md = exp10(th[k]), Rd = th[k + 1], ML = th[k + 2], kk = th[k + 3];
-        const double nl2Rd = -1.4426950408889634 / Rd;
-        const double Ad = 1.0e-6 * Md / (2.0 * PI * Rd * Rd * ci * ML);
-        const double inv2Rd = 0.5 / Rd;
-        const double Kd = 2.0 * G_KPC * Md / Rd;
-        gr[k] = (cb[o + 1] * Ad + cb[o + 3] * Kd) * LN10;
-        gr[k + 1] = -(cb[o + 0] * nl2Rd + 2.0 * cb[o + 1] * Ad + cb[o + 2] * inv2Rd + cb[o + 3] * Kd) / Rd;
-        gr[k + 2] = -cb[o + 1] * Ad / ML + cb[o + 6];
-        gr[k + 3] = -cb[o + 4] * si - cb[o + 5] * 2.0 * kk / 3.0;
-        gr[3] += (cb[o + 1] * Ad * si / ci - cb[o + 4] * kk * ci) * d2r;
-        k += 4;
-    }
-    if (g.halo == 2) {
-        const double M200 = exp10(th[k]), conc = th[k + 1];
-        const double r200 = cbrt(3.0 * M200 / (4.0 * PI * 200.0 * g.rho_crit));
-        const double rs = r200 / conc;
-        const double muc = log1p(conc) - conc / (1.0 + conc);
-        const double H0 = 1.0 / rs, H1 = G_KPC * M200 / (rs * muc);
-        const double dmu = conc / ((1.0 + conc) * (1.0 + conc));
-        gr[k] = (-cb[C_H0] * H0 / 3.0 + cb[C_H1] * H1 * 2.0 / 3.0) * LN10;
-        gr[k + 1] = cb[C_H0] / r200 + cb[C_H1] * H1 * (1.0 / conc - dmu / muc);
-        k += 2;
-    } else if (g.halo == 1) {
-        const double H1 = G_KPC * exp10(th[k]);
-        gr[k] = cb[C_H1] * H1 * LN10;
-        gr[k + 1] = cb[C_H0];
-        k += 2;
-    }
-    if (accum)
-        for (int q = 0; q < k; ++q) out[q] += gr[q];
-    else
-        for (int q = 0; q < stride; ++q) out[q] = q < k ? gr[q] : 0.0;
-}
-
-template <int BULGE, int NDISC, int HALO>
-__global__ void __launch_bounds__(256) adj_kernel(AdjArgs a) {
-    extern __shared__ __align__(16) float smem[];
-    const int tid = threadIdx.x, BS = blockDim.x;
-    const int band = blockIdx.x % a.nbands;
-    const int b = blockIdx.x / a.nbands;
-    const GridGeom& G = a.geo;
-    const int s = G.s, pad = G.pad, hs = G.hs;
-    const int by = band / a.nbx, bx = band - by * a.nbx;
-    const int j0 = by * a.band_h, j1 = min(G.ny, j0 + a.band_h);
-    const int c0 = bx * a.band_w, c1 = min(G.nx, c0 + a.band_w);
-    const int NR = j1 - j0, NC = c1 - c0;
-    const int NFR = (NR - 1) * s + 2 * pad + 1;
-    const int vlo = j0 * s + hs, ubase = c0 * s + hs;
-    const int nfrm = nfr_max(a.band_h, s, pad);
-    float* s_tab = smem;
-    float4* s_fb = (float4*)(smem + TAB_ALL);                    // [NR][NC]
-    float* s_gw = smem + TAB_ALL + 4 * a.band_h * a.band_w;       // [64]
-    int* s_lo = (int*)(s_gw + 64);
-    int* s_start = s_lo + nfrm;                                    // [nfrm + 1]
-    double* s_red = (double*)(((uintptr_t)(s_start + nfrm + 1) + 15) & ~(uintptr_t)15);
-    int2* s_span = (int2*)(s_red + RED_SLOTS * NCONST);           // [band_h] row spans
-    int* s_aof = (int*)(s_span + a.band_h);                        // [pad + 1] half-widths
-
-    const double* th = a.theta + (size_t)b * a.stride;
-    const TC tc = uniform_tc(make_tc(th, G));
-    if (!tc.valid) {
-        if (band == 0 && !a.accum)
-            for (int q = tid; q < a.stride; q += BS) a.grad[(size_t)b * a.stride + q] = 0.0;
-        return;
-    }
-    const float* tgh = BULGE == 2 ? gk_tab_jgh : gk_tab_gh;
-    for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = tgh[i];
-    for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
-    for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
-    for (int i = tid; i < 64; i += BS) s_gw[i] = a.gw[i];
-    for (int i = tid; i < NR; i += BS) s_span[i] = a.span[j0 + i];
-    for (int i = tid; i <= pad; i += BS) s_aof[i] = a.aof[i];
-    const size_t boff = (size_t)b * 4 * G.ny * G.nx, mstr = (size_t)G.ny * G.nx;
-    for (int p = tid; p < NR * NC; p += BS) {
-        const int jj = p / NC, cc = p - jj * NC;
-        const size_t pix = boff + (size_t)(j0 + jj) * G.nx + c0 + cc;
-        s_fb[p] = make_float4(a.fbar[pix], a.fbar[pix + mstr], a.fbar[pix + 2 * mstr], a.fbar[pix + 3 * mstr]);
-    }
-    __syncthreads();
-    for (int r = tid; r < NFR; r += BS) {
-        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
-        const int jhi = min(NR - 1, r / s);
-        int lo = 1 << 30, hi = -(1 << 30);
-        for (int jj = jlo; jj <= jhi; ++jj) {
-            int bb = r - jj * s - pad;
-            bb = bb < 0 ? -bb : bb;
-            const int2 sp = s_span[jj];
-            const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
-            if (cl <= ch) {
-                const int A = s_aof[bb];
-                lo = min(lo, cl * s + hs + pad - A);
-                hi = max(hi, ch * s + hs + pad + A);
-            }
-        }
-        const int w = hi >= lo ? hi - lo + 1 : 0;
-        s_lo[r] = w ? lo - ubase : 0;
-        s_start[r] = w;
-    }
-    __syncthreads();
-    const int total = block_exclusive_scan(s_start, NFR, (int*)s_red);
-    if (tid == 0) s_start[NFR] = total;
-    __syncthreads();
-
-    const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
-                 (const float4*)(s_tab + TAB_GH + TAB_PHI)};
-    float ad[NCONST];
-#pragma unroll
-    for (int k = 0; k < NCONST; ++k) ad[k] = 0.0f;
-    const float invW = a.invW;
-    const float inv_s = 1.0f / (float)s;
-    const int D = a.D;
-    int rcur = 0;
-    for (int q = tid; q < total; q += BS) {
-        while (s_start[rcur + 1] <= q) ++rcur;
-        const int r = rcur;
-        const int x = s_lo[r] + (q - s_start[r]);
-        // transposed stencil: this lattice point's share of every band pixel
-        // whose 3 sigma disc contains it, weighted by that pixel's adjoint
-        float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
-        // pixel rows jj = jq - d and columns cc = cq - k around the point; the
-        // divisions by s go through a float reciprocal (exact for these sizes)
-        const int jq = (int)(((float)r + 0.5f) * inv_s), rr = r - jq * s - pad;
-        const int cq = (int)(((float)x + 0.5f) * inv_s), rx = x - cq * s - pad;
-        const int jlo = max(0, jq - D), jhi = min(NR - 1, jq);
-        for (int jj = jlo; jj <= jhi; ++jj) {
-            int bb = rr + (jq - jj) * s;
-            bb = bb < 0 ? -bb : bb;
-            if (bb > pad) continue;
-            const int A = s_aof[bb];
-            const float gb = s_gw[bb];
-            // columns with |x - cc s - pad| <= A: k = cq - cc in [(pad - A - rx') / s, (pad + A - rx') / s]
-            const int klo = max(0, (int)floorf((float)(-A - rx + s - 1) * inv_s + 1e-4f));
-            const int khi = min(D, (int)floorf((float)(A - rx) * inv_s + 1e-4f));
-            const int ccl = max(0, cq - khi), cch = min(NC - 1, cq - klo);
-            const float4* fbr = s_fb + jj * NC;
-            int cc = ccl;
-            int t0 = x - cc * s - pad;
-            for (; cc < cch; cc += 2, t0 -= 2 * s) {
-                // two taps per trip: both pairs of LDS reads are in flight together
-                const int a0 = t0 < 0 ? -t0 : t0;
-                const int t1 = t0 - s, a1 = t1 < 0 ? -t1 : t1;
-                const float g0 = s_gw[a0], g1 = s_gw[a1];
-                const float4 b0 = fbr[cc], b1 = fbr[cc + 1];
-                const float w0 = gb * g0, w1 = gb * g1;
-                f.x = fmaf(w1, b1.x, fmaf(w0, b0.x, f.x));
-                f.y = fmaf(w1, b1.y, fmaf(w0, b0.y, f.y));
-                f.z = fmaf(w1, b1.z, fmaf(w0, b0.z, f.z));
-                f.w = fmaf(w1, b1.w, fmaf(w0, b0.w, f.w));
-            }
-            if (cc == cch) {
-                const int a0 = t0 < 0 ? -t0 : t0;
-                const float w = gb * s_gw[a0];
-                const float4 fb = fbr[cc];
-                f.x = fmaf(w, fb.x, f.x);
-                f.y = fmaf(w, fb.y, f.y);
-                f.z = fmaf(w, fb.z, f.z);
-                f.w = fmaf(w, fb.w, f.w);
-            }
-        }
-        const float du = (float)(ubase + x - tc.Ui) - tc.Uf;
-        const float dv = (float)(vlo + r - tc.Vi) - tc.Vf;
-        float4 fo = make_float4(f.x * invW, f.y * invW, f.z * invW, f.w * invW);
-        if (G.lw) {
-            // the lattice carries (B, B v, B (sigma^2 + v^2), B / <L/M>): map their
-            // adjoints to those of (B, v, sigma, <L/M>) at this point
-            float pB, pV, pS, pL;
-            point_model<BULGE, NDISC, HALO>(tc, T, du, dv, pB, pV, pS, pL);
-            const float il = frcp(pL);
-            fo = make_float4(fo.x + fo.y * pV + fo.z * fmaf(pS, pS, pV * pV) + fo.w * il,
-                             fmaf(fo.y, pB, 2.0f * fo.z * pB * pV), 2.0f * fo.z * pB * pS,
-                             -fo.w * pB * il * il);
-        }
-        point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
-    }
-
-    // ---- FP64 reduction of the constant adjoints: waves (all constants
-    // stepped together, so the shuffles overlap), then bands in order
-    const int lane = tid & 63, wave = tid >> 6, nw = (BS + 63) >> 6;
-    {
-        double v[NCONST];
-#pragma unroll
-        for (int k = 0; k < NCONST; ++k) v[k] = (double)ad[k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-            for (int k = 0; k < NCONST; ++k) v[k] += __shfl_down(v[k], o, 64);
-        }
-        if (lane == 0)
-#pragma unroll
-            for (int k = 0; k < NCONST; ++k) s_red[wave * NCONST + k] = v[k];
-    }
-    __syncthreads();
-    double* gp = a.gpart + ((size_t)b * a.nbands + band) * NCONST;
-    if (tid < NCONST) {
-        double t = 0.0;
-        for (int w = 0; w < nw; ++w) t += s_red[w * NCONST + tid];
-        gp[tid] = t;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        bool last = true;
-        if (a.nbands > 1) {
-            const unsigned ticket = __hip_atomic_fetch_add(a.counters + b, 1u, __ATOMIC_ACQ_REL,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-            last = ticket == (unsigned)a.nbands - 1;
-        }
-        if (last) {
-            double cb[NCONST];
-            for (int k = 0; k < NCONST; ++k) cb[k] = 0.0;
-            for (int bnd = 0; bnd < a.nbands; ++bnd)
-                for (int k = 0; k < NCONST; ++k)
-                    cb[k] += __hip_atomic_load(a.gpart + ((size_t)b * a.nbands + bnd) * NCONST + k,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            chain_rule(th, G, cb, a.grad + (size_t)b * a.stride, a.stride, a.accum);
-            if (a.nbands > 1) __hip_atomic_store(a.counters + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
 
 // ============================================================================
 // HMC leapfrog update (elementwise over the batch)
@@ -873,11 +87,16 @@ struct gk_grid {
     int2* d_span = nullptr;
     double* d_partials = nullptr;
     unsigned* d_counters = nullptr;
-    float* d_fbar = nullptr;
-    double* d_gpart = nullptr;
+    float* d_fbar = nullptr;        // [grad_rows][4][ny][nx] pixel adjoints of one batch chunk
+    double* d_gpart = nullptr;      // [grad_rows][adj nbands][NCONST]
+    int2* d_adj_vt = nullptr;       // adjoint tables (AdjArgs::vt, AdjArgs::ht)
+    int2* d_adj_ht = nullptr;
     double* d_logdet = nullptr;
     std::vector<LaunchRule> rules;
-    int adj_band_h = 0, adj_band_w = 0;
+    // adjoint launch: bands of adj_band_h x adj_band_w pixels, adj_rows lattice
+    // rows per phase; gradients of larger batches run in chunks of grad_rows
+    int adj_band_h = 0, adj_band_w = 0, adj_rows = 1, adj_nbands = 0, adj_lds = 0;
+    int adj_KP = 2, adj_nlev = 1, grad_rows = 1, gpart_bands = 0;   // gpart_bands: d_gpart capacity per row
 };
 
 static int valid_desc(const gk_grid_desc* d) {
@@ -907,7 +126,8 @@ static int valid_desc(const gk_grid_desc* d) {
 
 static void free_grid(gk_grid* g) {
     void* bufs[] = {g->d_gw, g->d_aof, g->d_tab, g->d_val, g->d_ivar,
-                    g->d_span, g->d_partials, g->d_counters, g->d_fbar, g->d_gpart, g->d_logdet};
+                    g->d_span, g->d_partials, g->d_counters, g->d_fbar, g->d_gpart, g->d_logdet,
+                    g->d_adj_vt, g->d_adj_ht};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete g;
@@ -980,6 +200,118 @@ static int default_rules(gk_grid* g) {
     return GK_OK;
 }
 
+// ---------------------------------------------------------------------------
+// adjoint launch shape
+// ---------------------------------------------------------------------------
+// LDS of one adjoint workgroup: at most 80 KiB (two per CU); shapes within
+// 53 KiB (three per CU) are preferred by the default rule
+constexpr int ADJ_LDS_MAX = 80 * 1024;
+constexpr int ADJ_LDS_3 = 53 * 1024;
+
+static int adj_ring_rows(const gk_grid* g, int rows) { return g->D + 1 + (rows - 1 + g->geo.s - 1) / g->geo.s; }
+
+static int adj_lds_of(const gk_grid* g, int bh, int bw, int rows) {
+    return adj_layout(bh, bw, g->geo.s, g->geo.pad, g->D, rows, g->adj_nlev, adj_ring_rows(g, rows), g->adj_KP)
+        .total_bytes;
+}
+
+// Fraction of the workgroup's thread slots busy in a phase of `rows` lattice
+// rows over a full-width band (the phase's points are spread flat over the
+// threads)
+static double adj_fill(int s, int pad, int bw, int rows) {
+    const int pts = rows * ((bw - 1) * s + 2 * pad + 1);
+    const int passes = (pts + ADJ_BS - 1) / ADJ_BS;
+    return (double)pts / ((double)passes * ADJ_BS);
+}
+
+// Install an adjoint shape (band_h x band_w pixels, `rows` lattice rows per
+// phase, 0 = chosen here) if it fits the kernel's limits.
+static int set_adj_shape(gk_grid* g, int bh, int bw, int rows) {
+    const int s = g->geo.s, pad = g->geo.pad;
+    bh = std::min(bh, g->d.ny);
+    bw = std::min(bw, g->d.nx);
+    if (bh < 1 || bw < 1) return fail(GK_EINVAL, "adjoint band must be at least 1 x 1");
+    if (bw > 128) return fail(GK_EINVAL, "adjoint band_w %d > 128", bw);
+    const int nb = ((g->d.nx + bw - 1) / bw) * ((g->d.ny + bh - 1) / bh);
+    if (nb > MAX_BANDS_ADJ) return fail(GK_EINVAL, "adjoint shape gives %d bands (> %d)", nb, MAX_BANDS_ADJ);
+    if (rows < 0 || rows > RS_CAP) return fail(GK_EINVAL, "adjoint rows must be in [0, %d]", RS_CAP);
+    int best = 0;
+    if (rows > 0) {
+        best = adj_lds_of(g, bh, bw, rows) <= ADJ_LDS_MAX ? rows : 0;
+    } else {
+        // best thread fill among the shapes that leave room for three
+        // workgroups per CU, else among those that fit at all
+        for (int cap : {ADJ_LDS_3, ADJ_LDS_MAX}) {
+            double fill = -1.0;
+            for (int r = 1; r <= RS_CAP; ++r) {
+                if (adj_lds_of(g, bh, bw, r) > cap) break;
+                const double f = adj_fill(s, pad, bw, r);
+                if (f >= fill - 1e-9) {
+                    fill = f;
+                    best = r;
+                }
+            }
+            if (best) break;
+        }
+    }
+    if (!best) return fail(GK_EINVAL, "adjoint band %d x %d needs more than %d KiB of LDS", bh, bw, ADJ_LDS_MAX / 1024);
+    g->adj_band_h = bh;
+    g->adj_band_w = bw;
+    g->adj_rows = best;
+    g->adj_nbands = nb;
+    g->adj_lds = adj_lds_of(g, bh, bw, best);
+    return GK_OK;
+}
+
+// Default adjoint shape (measured on the 80 x 80, 100 x 100 and 300 x 300
+// benchmark grids): the widest band (columns split evenly, at most 80) whose
+// phases keep >= 90 % of the threads busy with at least two lattice rows per
+// phase, within the LDS that leaves room for three workgroups per CU; rows
+// per phase: the best fill, then the fewest rows (a larger row buffer costs
+// occupancy).  Bands are up to 64 rows tall, taller when the grid would need
+// more than MAX_BANDS_ADJ bands.  A grid whose adjoint fits no shape keeps
+// adj_nbands = 0: its forward calls work and its gradient calls return
+// GK_EINVAL.
+static int default_adj_shape(gk_grid* g) {
+    const int nx = g->d.nx, ny = g->d.ny, s = g->geo.s, pad = g->geo.pad;
+    const std::string saved = g_err;
+    auto split = [](int n, int m) { const int k = (n + m - 1) / m; return (n + k - 1) / k; };
+    for (int cap : {ADJ_LDS_3, ADJ_LDS_MAX})
+        for (int hmax = 64; hmax <= 4096; hmax *= 2) {
+            const int bh = split(ny, hmax);
+            int bbw = 0, brows = 0;
+            double bfill = -1.0;
+            for (int wmax : {80, 64, 40, 32, 20, 16, 8}) {
+                const int bw = split(nx, wmax);
+                if (((nx + bw - 1) / bw) * ((ny + bh - 1) / bh) > MAX_BANDS_ADJ) continue;
+                int rows = 0;
+                double fill = -1.0;
+                for (int r : {2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 1}) {
+                    if (adj_lds_of(g, bh, bw, r) > cap) continue;
+                    const double f = adj_fill(s, pad, bw, r);
+                    if (f > fill + 1e-9) {
+                        fill = f;
+                        rows = r;
+                    }
+                }
+                if (!rows) continue;
+                if (fill > bfill + 1e-9) {
+                    bfill = fill;
+                    bbw = bw;
+                    brows = rows;
+                }
+                if (fill >= 0.9 && rows >= 2) break;
+            }
+            if (bbw && set_adj_shape(g, bh, bbw, brows) == GK_OK) {
+                g_err = saved;
+                return GK_OK;
+            }
+        }
+    g_err = saved;
+    g->adj_nbands = 0;
+    return GK_OK;
+}
+
 struct LaunchCfg {
     int band_h, band_w, nbx, nbands, BS, gsub, xw, lds;
 };
@@ -1029,28 +361,11 @@ static void fit_shape(const gk_grid* g, int& bh, int& bw, int bs_fixed) {
 }
 
 template <int MODE>
-static hipError_t launch_fwd(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, int B, hipStream_t st) {
-    const int bulge = g->d.bulge, nd = g->d.n_discs, halo = g->d.halo;
+static hipError_t enqueue_fwd(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, int B, hipStream_t st) {
     if ((size_t)B * c.nbands * c.BS >= ((size_t)1 << 31)) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)(B * c.nbands)), block((unsigned)c.BS);
-#define GK_LAUNCH(BU, ND, HA)                                                                    \
-    if (bulge == BU && nd == ND && halo == HA) {                                                  \
-        if (a.geo.lw)                                                                             \
-            hipLaunchKernelGGL((fwd_kernel<BU, ND, HA, MODE, 1>), grid, block, c.lds, st, a);    \
-        else                                                                                      \
-            hipLaunchKernelGGL((fwd_kernel<BU, ND, HA, MODE, 0>), grid, block, c.lds, st, a);    \
-        return hipGetLastError();                                                                 \
-    }
-    GK_LAUNCH(1, 0, 0) GK_LAUNCH(1, 0, 1) GK_LAUNCH(1, 0, 2)
-    GK_LAUNCH(1, 1, 0) GK_LAUNCH(1, 1, 1) GK_LAUNCH(1, 1, 2)
-    GK_LAUNCH(1, 2, 0) GK_LAUNCH(1, 2, 1) GK_LAUNCH(1, 2, 2)
-    GK_LAUNCH(2, 0, 0) GK_LAUNCH(2, 0, 1) GK_LAUNCH(2, 0, 2)
-    GK_LAUNCH(2, 1, 0) GK_LAUNCH(2, 1, 1) GK_LAUNCH(2, 1, 2)
-    GK_LAUNCH(2, 2, 0) GK_LAUNCH(2, 2, 1) GK_LAUNCH(2, 2, 2)
-    GK_LAUNCH(0, 1, 0) GK_LAUNCH(0, 1, 1) GK_LAUNCH(0, 1, 2)
-    GK_LAUNCH(0, 2, 0) GK_LAUNCH(0, 2, 1) GK_LAUNCH(0, 2, 2)
-#undef GK_LAUNCH
-    return hipErrorInvalidValue;
+    return a.geo.lw ? launch_fwd<MODE, 1>(g->d.bulge, g->d.n_discs, g->d.halo, grid, block, c.lds, st, a)
+                    : launch_fwd<MODE, 0>(g->d.bulge, g->d.n_discs, g->d.halo, grid, block, c.lds, st, a);
 }
 
 static int check_call(const gk_grid* g, const double* theta, int B, int stride, const void* out) {
@@ -1297,7 +612,62 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
                 tab[(size_t)ph * DSTRIDE + d] = make_int2(aof[std::abs(bb)], wb);
             }
         }
+    // adjoint tables (transposed stencil in separable form): for each lattice
+    // row phase, the lags in reach sorted by decreasing half-width and grouped
+    // by equal half-width; for each (row phase, column phase) the D + 1 pixel
+    // columns in reach with their weight and group count
+    std::vector<int2> avt((size_t)s * DSTRIDE, make_int2(0, 0));
+    std::vector<std::vector<int>> groupA(s);
+    int nlev = 1;
+    for (int ph = 0; ph < s; ++ph) {
+        std::vector<std::pair<int, int>> lags;         // (A, d)
+        for (int d = 0; d <= D; ++d) {
+            const int bb = std::abs(d * s + ph - pad);
+            if (bb <= pad) lags.push_back({aof[bb], d});
+        }
+        std::sort(lags.begin(), lags.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+            return x.first != y.first ? x.first > y.first : x.second < y.second;
+        });
+        int grp = -1;
+        for (size_t n = 0; n < lags.size(); ++n) {
+            const int A = lags[n].first, d = lags[n].second;
+            if (n == 0 || A != lags[n - 1].first) {
+                ++grp;
+                groupA[ph].push_back(A);
+            }
+            const int last = (n + 1 == lags.size() || lags[n + 1].first != A) ? 1 : 0;
+            const float w = gw[std::abs(d * s + ph - pad)];
+            int wb;
+            std::memcpy(&wb, &w, 4);
+            avt[(size_t)ph * DSTRIDE + n] = make_int2(d | (grp << 8) | (last << 16), wb);
+        }
+        nlev = std::max(nlev, (int)groupA[ph].size());
+    }
+    const int KP = (D + 2) & ~1;                       // even, >= D + 1
+    std::vector<int2> aht((size_t)s * s * KP, make_int2(0, 0));
+    for (int ph = 0; ph < s; ++ph)
+        for (int i = 0; i < s; ++i)
+            for (int k = 0; k <= D; ++k) {
+                const int at = std::abs(k * s + i - pad);
+                int l = 0;
+                for (int A : groupA[ph]) l += A >= at ? 1 : 0;
+                if (l == 0) continue;
+                int wb;
+                std::memcpy(&wb, &gw[at], 4);
+                aht[((size_t)ph * s + i) * KP + k] = make_int2(-k * nlev + (l - 1), wb);
+            }
+    g->adj_KP = KP;
+    g->adj_nlev = nlev;
     const size_t npix = (size_t)desc->nx * desc->ny;
+    // the gradient's pixel-adjoint buffer holds at most ~2 GiB: larger batches
+    // run in chunks of grad_rows vectors (one forward + adjoint pair each)
+    g->grad_rows = (int)std::max<size_t>(1, std::min<size_t>((size_t)max_batch,
+                                                              ((size_t)2 << 30) / (16 * npix)));
+    int arc = default_adj_shape(g);
+    if (arc) {
+        delete g;
+        return arc;
+    }
 #define ALLOC(ptr, bytes)                                                                \
     if (hipMalloc((void**)&(ptr), (bytes)) != hipSuccess) {                              \
         free_grid(g);                                                                    \
@@ -1311,8 +681,11 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
     ALLOC(g->d_span, sizeof(int2) * desc->ny);
     ALLOC(g->d_partials, sizeof(double) * (size_t)max_batch * MAX_BANDS);
     ALLOC(g->d_counters, sizeof(unsigned) * (size_t)max_batch);
-    ALLOC(g->d_fbar, sizeof(float) * 4 * npix * (size_t)max_batch);
-    ALLOC(g->d_gpart, sizeof(double) * NCONST * MAX_BANDS_ADJ * (size_t)max_batch);
+    ALLOC(g->d_fbar, sizeof(float) * 4 * npix * (size_t)g->grad_rows);
+    g->gpart_bands = std::max(1, g->adj_nbands);
+    ALLOC(g->d_gpart, sizeof(double) * NCONST * g->gpart_bands * (size_t)g->grad_rows);
+    ALLOC(g->d_adj_vt, sizeof(int2) * avt.size());
+    ALLOC(g->d_adj_ht, sizeof(int2) * aht.size());
     ALLOC(g->d_logdet, sizeof(double));
 #undef ALLOC
     {
@@ -1328,24 +701,14 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
     if (hipMemcpy(g->d_gw, gw64.data(), sizeof(float) * gw64.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(g->d_aof, aof.data(), sizeof(int) * (pad + 1), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(g->d_tab, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_adj_vt, avt.data(), sizeof(int2) * avt.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_adj_ht, aht.data(), sizeof(int2) * aht.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(g->d_counters, 0, sizeof(unsigned) * (size_t)max_batch) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         free_grid(g);
         return fail(GK_EHIP, "upload of the stencil tables failed");
     }
     default_rules(g);
-    // adjoint bands: at most 40 x 40 pixels (pixel adjoints are staged in LDS)
-    g->adj_band_w = std::min(desc->nx, 40);
-    g->adj_band_h = std::min(desc->ny, 40);
-    while ((desc->nx + g->adj_band_w - 1) / g->adj_band_w * ((desc->ny + g->adj_band_h - 1) / g->adj_band_h) >
-           MAX_BANDS_ADJ) {
-        g->adj_band_w = std::min(desc->nx, g->adj_band_w + 8);
-        g->adj_band_h = std::min(desc->ny, g->adj_band_h + 8);
-    }
-    if (adj_lds_bytes(g->adj_band_h, g->adj_band_w, s, pad) > 64 * 1024) {
-        free_grid(g);
-        return fail(GK_EINVAL, "grid too large for the adjoint's LDS tiles in this build");
-    }
     *out = g;
     return GK_OK;
 }
@@ -1380,6 +743,40 @@ int get_launch_shape(gk_grid_t g, int B, int* band_h, int* band_w, int* steps) {
     if (!g || !band_h || !band_w || !steps) return fail(GK_EINVAL, "NULL grid or output pointer");
     if (B < 1) return fail(GK_EINVAL, "B must be >= 1");
     return choose_rule(g, B, *band_h, *band_w, *steps);
+}
+
+int set_adjoint_shape(gk_grid_t g, int band_h, int band_w, int rows) {
+    if (!g) return fail(GK_EINVAL, "grid is NULL");
+    if (band_h < 1 || band_w < 1) return fail(GK_EINVAL, "band_h, band_w must be >= 1");
+    const int old[5] = {g->adj_band_h, g->adj_band_w, g->adj_rows, g->adj_nbands, g->adj_lds};
+    int rc = set_adj_shape(g, band_h, band_w, rows);   // changes g only on success
+    if (rc) return rc;
+    if (g->adj_nbands > g->gpart_bands) {
+        // more bands than the per-band gradient partials were sized for: grow them
+        double* p = nullptr;
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMalloc((void**)&p, sizeof(double) * NCONST * g->adj_nbands * (size_t)g->grad_rows) != hipSuccess) {
+            g->adj_band_h = old[0];
+            g->adj_band_w = old[1];
+            g->adj_rows = old[2];
+            g->adj_nbands = old[3];
+            g->adj_lds = old[4];
+            return fail(GK_ENOMEM, "allocation of the adjoint's band partials failed");
+        }
+        (void)hipFree(g->d_gpart);
+        g->d_gpart = p;
+        g->gpart_bands = g->adj_nbands;
+    }
+    return GK_OK;
+}
+
+int get_adjoint_shape(gk_grid_t g, int* band_h, int* band_w, int* rows) {
+    if (!g || !band_h || !band_w || !rows) return fail(GK_EINVAL, "NULL grid or output pointer");
+    if (g->adj_nbands <= 0) return fail(GK_EINVAL, "this grid fits no adjoint band shape of this build");
+    *band_h = g->adj_band_h;
+    *band_w = g->adj_band_w;
+    *rows = g->adj_rows;
+    return GK_OK;
 }
 
 int set_data(gk_grid_t g, const float* value, const float* err, int on_device, void* stream) {
@@ -1450,7 +847,7 @@ static int run_loglike(gk_grid* g, const double* theta, int B, int stride, doubl
     fill_args(g, c, a, theta, stride);
     a.logL = logL;
     a.accum = accum;
-    hipError_t e = launch_fwd<MODE_LOGL>(g, c, a, B, st);
+    hipError_t e = enqueue_fwd<MODE_LOGL>(g, c, a, B, st);
     if (e != hipSuccess) return fail(GK_EHIP, "forward launch failed: %s", hipGetErrorString(e));
     return GK_OK;
 }
@@ -1479,7 +876,7 @@ int eval_maps(gk_grid_t g, const double* theta, int B, int stride, float* maps, 
     fill_args(g, c, a, theta, stride);
     a.maps = maps;
     a.map_mask = 15;
-    hipError_t e = launch_fwd<MODE_MAPS>(g, c, a, B, (hipStream_t)stream);
+    hipError_t e = enqueue_fwd<MODE_MAPS>(g, c, a, B, (hipStream_t)stream);
     if (e != hipSuccess) return fail(GK_EHIP, "maps launch failed: %s", hipGetErrorString(e));
     return GK_OK;
 }
@@ -1496,59 +893,58 @@ int loglike_grad_batch(gk_grid_t g, const double* theta, int B, int stride, doub
 
 static int run_grad(gk_grid* g, const double* theta, int B, int stride, double* logL, double* grad, int accum,
                     hipStream_t st) {
-    // pass 1: log-likelihood and d logL / d F at every pixel
+    if (g->adj_nbands <= 0)
+        return fail(GK_EINVAL, "this grid (%d x %d, s = %d) fits no adjoint band shape of this build", g->d.nx,
+                    g->d.ny, g->geo.s);
+    // the whole batch's forward launch shape (band partials and tickets per row)
     int bh, bw, steps;
     choose_rule(g, B, bh, bw, steps);
     LaunchCfg c;
     int rc = make_cfg(g, bh, bw, c, 0, steps);
     if (rc) return rc;
-    FwdArgs fa;
-    fill_args(g, c, fa, theta, stride);
-    fa.logL = logL;
-    fa.fbar = g->d_fbar;
-    fa.accum = accum;
-    hipError_t e = launch_fwd<MODE_FBAR>(g, c, fa, B, st);
-    if (e != hipSuccess) return fail(GK_EHIP, "forward (adjoint seed) launch failed: %s", hipGetErrorString(e));
-    // pass 2: adjoint of the PSF and of the model, chain rule to theta
-    AdjArgs aa;
-    aa.geo = g->geo;
-    aa.gw = g->d_gw;
-    aa.aof = g->d_aof;
-    aa.invW = g->invW;
-    aa.D = g->D;
-    aa.span = g->d_span;
-    aa.band_h = g->adj_band_h;
-    aa.band_w = g->adj_band_w;
-    aa.nbx = (g->d.nx + aa.band_w - 1) / aa.band_w;
-    aa.nbands = aa.nbx * ((g->d.ny + aa.band_h - 1) / aa.band_h);
-    aa.theta = theta;
-    aa.stride = stride;
-    aa.fbar = g->d_fbar;
-    aa.gpart = g->d_gpart;
-    aa.counters = g->d_counters;
-    aa.grad = grad;
-    aa.accum = accum;
-    const int lds = adj_lds_bytes(aa.band_h, aa.band_w, g->geo.s, g->geo.pad);
-    const dim3 grid2((unsigned)(B * aa.nbands)), block2(256);
-    const int bulge = g->d.bulge, nd = g->d.n_discs, halo = g->d.halo;
-    bool launched = false;
-#define GK_ALAUNCH(BU, ND, HA)                                                                  \
-    if (!launched && bulge == BU && nd == ND && halo == HA) {                                    \
-        hipLaunchKernelGGL((adj_kernel<BU, ND, HA>), grid2, block2, lds, st, aa);               \
-        launched = true;                                                                         \
+    // chunks of at most grad_rows vectors share the pixel-adjoint buffer
+    for (int r0 = 0; r0 < B; r0 += g->grad_rows) {
+        const int n = std::min(g->grad_rows, B - r0);
+        const double* th = theta + (size_t)r0 * stride;
+        // pass 1: log-likelihood and d logL / d F at every pixel
+        FwdArgs fa;
+        fill_args(g, c, fa, th, stride);
+        fa.logL = logL + r0;
+        fa.fbar = g->d_fbar;
+        fa.accum = accum;
+        hipError_t e = enqueue_fwd<MODE_FBAR>(g, c, fa, n, st);
+        if (e != hipSuccess)
+            return fail(GK_EHIP, "forward (adjoint seed) launch failed: %s", hipGetErrorString(e));
+        // pass 2: transposed stencil and reverse point model per band, chain rule to theta
+        AdjArgs aa;
+        aa.geo = g->geo;
+        aa.aof = g->d_aof;
+        aa.vt = g->d_adj_vt;
+        aa.ht = (const int4*)g->d_adj_ht;
+        aa.KP = g->adj_KP;
+        aa.nlev = g->adj_nlev;
+        aa.rb = adj_ring_rows(g, g->adj_rows);
+        aa.invW = g->invW;
+        aa.D = g->D;
+        aa.span = g->d_span;
+        aa.band_h = g->adj_band_h;
+        aa.band_w = g->adj_band_w;
+        aa.nbx = (g->d.nx + aa.band_w - 1) / aa.band_w;
+        aa.nbands = g->adj_nbands;
+        aa.rows = g->adj_rows;
+        aa.theta = th;
+        aa.stride = stride;
+        aa.fbar = g->d_fbar;
+        aa.gpart = g->d_gpart;
+        aa.counters = g->d_counters;
+        aa.grad = grad + (size_t)r0 * stride;
+        aa.accum = accum;
+        if ((size_t)n * aa.nbands >= ((size_t)1 << 31)) return fail(GK_EINVAL, "adjoint grid too large");
+        const dim3 grid2((unsigned)(n * aa.nbands)), block2(ADJ_BS);
+        e = g->geo.lw ? launch_adj_lw<1>(g->d.bulge, g->d.n_discs, g->d.halo, grid2, block2, g->adj_lds, st, aa)
+                      : launch_adj_lw<0>(g->d.bulge, g->d.n_discs, g->d.halo, grid2, block2, g->adj_lds, st, aa);
+        if (e != hipSuccess) return fail(GK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
     }
-    GK_ALAUNCH(1, 0, 0) GK_ALAUNCH(1, 0, 1) GK_ALAUNCH(1, 0, 2)
-    GK_ALAUNCH(1, 1, 0) GK_ALAUNCH(1, 1, 1) GK_ALAUNCH(1, 1, 2)
-    GK_ALAUNCH(1, 2, 0) GK_ALAUNCH(1, 2, 1) GK_ALAUNCH(1, 2, 2)
-    GK_ALAUNCH(2, 0, 0) GK_ALAUNCH(2, 0, 1) GK_ALAUNCH(2, 0, 2)
-    GK_ALAUNCH(2, 1, 0) GK_ALAUNCH(2, 1, 1) GK_ALAUNCH(2, 1, 2)
-    GK_ALAUNCH(2, 2, 0) GK_ALAUNCH(2, 2, 1) GK_ALAUNCH(2, 2, 2)
-    GK_ALAUNCH(0, 1, 0) GK_ALAUNCH(0, 1, 1) GK_ALAUNCH(0, 1, 2)
-    GK_ALAUNCH(0, 2, 0) GK_ALAUNCH(0, 2, 1) GK_ALAUNCH(0, 2, 2)
-#undef GK_ALAUNCH
-    e = hipGetLastError();
-    if (!launched || e != hipSuccess)
-        return fail(GK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
     return GK_OK;
 }
 
@@ -1663,13 +1059,12 @@ int loglike_multi(const gk_grid_t* grids, int n_gal, const double* theta, const 
         }
     }
     const int n0 = p->n_items - p->n_items_lw;
+    hipError_t e = hipSuccess;
     if (n0 > 0)
-        hipLaunchKernelGGL(multi_kernel<0>, dim3((unsigned)n0), dim3(MULTI_BS), p->lds, st, p->d_args, p->d_items,
-                           theta, stride, logL);
-    if (p->n_items_lw > 0)
-        hipLaunchKernelGGL(multi_kernel<1>, dim3((unsigned)p->n_items_lw), dim3(MULTI_BS), p->lds, st, p->d_args,
-                           p->d_items + n0, theta, stride, logL);
-    hipError_t e = hipGetLastError();
+        e = launch_multi<0>(dim3((unsigned)n0), dim3(MULTI_BS), p->lds, st, p->d_args, p->d_items, theta, stride, logL);
+    if (e == hipSuccess && p->n_items_lw > 0)
+        e = launch_multi<1>(dim3((unsigned)p->n_items_lw), dim3(MULTI_BS), p->lds, st, p->d_args, p->d_items + n0,
+                            theta, stride, logL);
     if (e != hipSuccess) return fail(GK_EHIP, "many-grid launch failed: %s", hipGetErrorString(e));
     return GK_OK;
 }

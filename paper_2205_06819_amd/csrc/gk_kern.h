@@ -1,0 +1,153 @@
+// Kernel arguments, LDS layouts and the launch entry points shared by the
+// host code (galkin.hip) and the kernel translation units (fwd_inst.hip,
+// multi_inst.hip, adj.hip), which are compiled in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gk_device.h"
+
+namespace gk {
+
+enum { MODE_LOGL = 0, MODE_FBAR = 1, MODE_MAPS = 2 };
+constexpr int MAX_BANDS = 1024;       // per theta
+constexpr int RED_SLOTS = 16;         // waves per workgroup (<= 1024 threads)
+
+struct FwdArgs {
+    GridGeom geo;
+    const float* gw;        // [64] 1-D Gaussian factors exp(-a^2 / 2 (sigma s)^2), zero beyond pad
+    const int* aof;         // [pad + 1] half-width A(|b|) of the stencil at row offset b
+    const int2* tab;        // [s][DSTRIDE] (A(|b|), weight bits g(|b|)) for lattice-row phase ph and
+                            // pixel-row lag d, b = d s + ph - pad; (0, 0) where |b| > pad
+    float invW;             // 1 / sum of the 2-D stencil weights
+    int D;                  // floor(2 pad / s): lag at which a pixel row is complete
+    const float* val;       // data [4][ny][nx]
+    const float* ivar;      // inverse variances [4][ny][nx], 0 = masked
+    const int2* span;       // [ny] first / last column valid in any map
+    const double* logdet;   // sum of ln(2 pi e^2) over valid pixels (device scalar)
+    int band_h, band_w, nbx, nbands;
+    int pstride;            // row stride of partials (>= nbands)
+    int gsub;               // pixel-row steps per model phase (gsub * s <= RS_CAP lattice rows)
+    int xw;                 // row stride of the row buffer (floats)
+    int tpad;               // compile-time tap count used by the stencil (>= pad)
+    const double* theta;
+    int stride;
+    double* logL;
+    float* maps;            // MODE_MAPS output [B][4][ny][nx]
+    float* fbar;            // MODE_FBAR output [B][4][ny][nx]: d logL / d F
+    double* partials;       // [B][pstride]
+    unsigned* counters;     // [B]
+    int accum;              // 1: add the log-likelihood to logL[b] instead of storing it
+    int map_mask;           // bit m set: map m is convolved (maps with no valid pixel are skipped)
+};
+
+constexpr int DMAX = 10;        // largest lag D = floor(2 pad / s) supported
+constexpr int DSTRIDE = DMAX + 1;
+constexpr int RS_CAP = 16;      // lattice rows per model phase
+constexpr int GSUB_CAP = 4;     // pixel-row steps per model phase
+
+struct Layout {                 // LDS carve-up, identical on host and device
+    int tab, rows, red, rows_lo, rows_start, stage, fin, total_bytes;
+};
+
+__host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
+
+// nfin: floats of the per-step exchange buffer of the luminosity-weighted
+// mode (0 otherwise)
+__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int band_h, int nfin) {
+    Layout L;
+    int off = 0;                                   // in 4-byte words
+    L.rows = off;       off += rows * 4 * xw;
+    off = (off + 3) & ~3;
+    L.red = off;        off += 2 * RED_SLOTS;      // doubles
+    L.rows_lo = off;    off += nfrm;
+    L.rows_start = off; off += nfrm + 1 + RS_CAP;  // padded: phase lookups read ahead
+    off = (off + 1) & ~1;
+    L.stage = off;      off += 2 * band_h + 32;    // row spans and stencil half-widths
+    L.fin = off;        off += nfin;
+    // the tables last, at a launch-dependent offset: a table lookup is then one
+    // base add and four reads with immediate offsets
+    off = (off + 3) & ~3;
+    L.tab = off;        off += TAB_ALL;
+    L.total_bytes = 4 * off;
+    return L;
+}
+
+
+constexpr int MAX_BANDS_ADJ = 1024;   // per theta
+constexpr int ADJ_BS = 256;           // threads per workgroup of the adjoint
+
+// The adjoint applies the transposed PSF stencil in separable form.  For a
+// lattice row of phase ph (row index mod s) the pixel rows within reach sit
+// at lags d = 0..D (pixel row = current step - d) and vertical offsets
+// b_d = d s + ph - pad; sorted by decreasing half-width A(|b_d|) they fall
+// into groups of equal A.  Per (lattice row, pixel column) the vertical pass
+// stores the running sums S_l of g(|b_d|) rbar over groups 1..l; a lattice
+// point at horizontal offset t from a pixel column then takes g(|t|) S_l with
+// l = number of groups whose A >= |t|.
+struct AdjArgs {
+    GridGeom geo;
+    const int* aof;         // [pad + 1] stencil half-widths A(|b|)
+    const int2* vt;         // [s][DSTRIDE] vertical pass: (d | group << 8 | last-of-group << 16, weight bits)
+    const int4* ht;         // [s][s][KP / 2] horizontal taps in pairs: (S offset, weight bits) x 2
+    int KP;                 // horizontal taps per (phase, column phase), even, >= D + 1
+    int nlev;               // groups (S slots) per (lattice row, pixel column)
+    int rb;                 // rows of the pixel-adjoint ring buffer, D + 1 + ceil((rows - 1) / s)
+    float invW;
+    int D;                  // pixel-row lags of the stencil, floor(2 pad / s)
+    const int2* span;       // [ny] valid column spans
+    int band_h, band_w, nbx, nbands;
+    int rows;               // lattice rows per phase (1..RS_CAP)
+    const double* theta;
+    int stride;
+    const float* fbar;      // [rows][4][ny][nx] d logL / d F from the forward pass
+    double* gpart;          // [rows][nbands][NCONST] per-band constant adjoints
+    unsigned* counters;     // [rows], zero on entry, reset by the last band
+    double* grad;           // [rows][stride]
+    int accum;              // 1: add the gradient to grad[b] instead of storing it
+};
+
+struct AdjLayout {              // LDS carve-up of the adjoint (4-byte words), host and device
+    int tab, ring, S, vt, ht, red, lo, hi, span, aof, plo, pw, total_bytes;
+};
+
+__host__ __device__ inline AdjLayout adj_layout(int band_h, int band_w, int s, int pad, int D, int rows, int nlev,
+                                                int rb, int KP) {
+    AdjLayout L;
+    int off = 0;
+    L.tab = off;  off += TAB_ALL;
+    off = (off + 3) & ~3;
+    L.ring = off; off += rb * band_w * 4;                          // float4 [rb][band_w]
+    L.S = off;    off += rows * (band_w + 2 * D) * nlev * 4;       // float4 [rows][band_w + 2D][nlev]
+    L.ht = off;   off += s * s * KP * 2;                           // int4 [s][s][KP / 2]
+    L.vt = off;   off += s * DSTRIDE * 2;                          // int2 [s][DSTRIDE]
+    off = (off + 1) & ~1;
+    L.red = off;  off += RED_SLOTS * NCONST * 2;                   // doubles
+    const int nfrm = nfr_max(band_h, s, pad);
+    L.lo = off;   off += nfrm;
+    L.hi = off;   off += nfrm;
+    off = (off + 1) & ~1;
+    L.span = off; off += 2 * band_h;
+    L.aof = off;  off += pad + 1;
+    const int nch = (nfrm + rows - 1) / rows + 1;
+    L.plo = off;  off += nch;
+    L.pw = off;   off += nch;
+    L.total_bytes = 4 * off;
+    return L;
+}
+
+constexpr int MULTI_BS = 256;   // threads per workgroup of the many-grid launch
+
+// launch entry points (each defined in one kernel translation unit); they
+// enqueue one launch on the stream and return hipGetLastError()
+template <int MODE, int LW>
+hipError_t launch_fwd(int bulge, int ndisc, int halo, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                      const FwdArgs& a);
+template <int LW>
+hipError_t launch_multi(dim3 grid, dim3 block, size_t lds, hipStream_t st, const FwdArgs* grids, const int4* items,
+                        const double* theta, int stride, double* logL);
+template <int LW>
+hipError_t launch_adj_lw(int bulge, int ndisc, int halo, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                         const AdjArgs& a);
+
+}  // namespace gk

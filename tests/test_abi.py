@@ -59,6 +59,8 @@ def test_argument_errors_without_device():
     assert lib.get_launch_shape(None, 1, None, None, None) == gk.GK_EINVAL
     assert lib.loglike_joint(None, 0, None, 1, 13, None, None, None) == gk.GK_EINVAL
     assert lib.set_launch_shape(None, 1, 1, 1, 0) == gk.GK_EINVAL
+    assert lib.set_adjoint_shape(None, 40, 40, 0) == gk.GK_EINVAL
+    assert lib.get_adjoint_shape(None, None, None, None) == gk.GK_EINVAL
     assert lib.loglike_multi(None, -1, None, None, 13, None, None, None) == gk.GK_EINVAL
     assert lib.loglike_multi(None, 0, None, None, 13, None, None, None) == gk.GK_OK
     assert lib.loglike_multi(None, 2, None, None, 13, None, None, None) == gk.GK_EINVAL

@@ -58,3 +58,16 @@ def test_luminosity_weighted_and_single_map_counts():
     assert bench.flops_per_pixel(lw) == 509 + 7
     wp, _ = W.multires_pair()
     assert bench.flops_per_pixel(wp.spec, 1) == 1 * (1 * (1 + 3 * 5) + 2 * 11 + 5) + 1
+
+
+def test_adjoint_work_counts():
+    """Per needed lattice point: frame 49, Hernquist bulge 105, two discs 2 x 72,
+    NFW 40, combination 44 (= 382), plus the transposed stencil 8 (D + 1) + 4
+    + 8 (D + 1) / s."""
+    spec = W.workload("realistic").spec          # s = 3, pad = 9, D = 6
+    assert bench.flops_adjoint_per_point(spec) == 382 + 56 + 4 + 19
+    st = W.workload("stress").spec               # s = 5, pad = 25, D = 10
+    assert bench.stencil_pad(st) == 25
+    assert bench.flops_adjoint_per_point(st) == 382 + 88 + 4 + 18
+    lw = W.workload("lw").spec
+    assert bench.flops_adjoint_per_point(lw) == 382 + 157 + 12 + 56 + 4 + 19
