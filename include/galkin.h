@@ -118,6 +118,21 @@ int set_data(gk_grid_t grid, const float* value, const float* err, int on_device
 int loglike_batch(gk_grid_t grid, const double* theta, int B, int stride, double* logL,
                   void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * log-likelihoods as loglike_batch, with the launch's scratch (per-vector band
+ * tickets and FP64 band partials) taken from a fixed array of 16 MiB that
+ * each device holds from library load until the process ends, instead of the
+ * grid's workspace.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and clears the tickets with a kernel.  It needs
+ * B x (4 + 8 nbands) bytes of scratch, nbands being the bands of the launch
+ * shape for B (get_launch_shape); larger requests return GK_EINVAL.  All such
+ * calls on one device share the array: calls that overlap in time on one
+ * device (different streams or threads) race and must be serialised by the
+ * caller.  The grid must live on the current device. */
+int loglike_batch_noalloc(gk_grid_t grid, const double* theta, int B, int stride, double* logL,
+                          void* hip_stream);
+
 /* As loglike_batch, and also grad[b][k] = d logL[b] / d theta[b][k] for
  * k < P (columns P..stride-1 of grad are set to 0).  grad: device float64
  * [B][stride].  The gradient is the exact derivative of the FP32 model

@@ -29,7 +29,8 @@ GK_PSF_MAPS, GK_PSF_LUMINOSITY = 0, 1
 
 EXPORTS = ("create_grid", "destroy_grid", "n_params", "set_data", "loglike_batch",
            "loglike_grad_batch", "eval_maps", "set_launch_shape", "hmc_leapfrog", "loglike_multi", "loglike_joint", "get_launch_shape", "ml_from_colour",
-           "brightness_errors", "set_adjoint_shape", "get_adjoint_shape", "last_error")
+           "brightness_errors", "set_adjoint_shape", "get_adjoint_shape", "loglike_batch_noalloc",
+           "last_error")
 
 
 class GalkinError(RuntimeError):
@@ -60,6 +61,7 @@ def _load() -> ctypes.CDLL:
     lib.n_params.argtypes = [vp]
     lib.set_data.argtypes = [vp, vp, vp, i, vp]
     lib.loglike_batch.argtypes = [vp, vp, i, i, vp, vp]
+    lib.loglike_batch_noalloc.argtypes = [vp, vp, i, i, vp, vp]
     lib.loglike_grad_batch.argtypes = [vp, vp, i, i, vp, vp, vp]
     lib.eval_maps.argtypes = [vp, vp, i, i, vp, vp]
     lib.set_launch_shape.argtypes = [vp, i, i, i, i]
@@ -154,6 +156,18 @@ def loglike_batch(handle: int, theta: torch.Tensor, out: Optional[torch.Tensor] 
         out = torch.empty(B, dtype=torch.float64, device=theta.device)
     _check(_lib.loglike_batch(handle, theta.data_ptr(), B, theta.stride(0), out.data_ptr(),
                               _stream(stream)))
+    return out
+
+
+def loglike_batch_noalloc(handle: int, theta: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """loglike_batch with the launch's scratch in the library's fixed device
+    array (nothing is allocated: out must be given, float64 [B] on the device)."""
+    theta = _theta(theta, n_params(handle))
+    B = theta.shape[0]
+    if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= B):
+        raise ValueError("out must be a contiguous float64 CUDA tensor of at least B elements")
+    _check(_lib.loglike_batch_noalloc(handle, theta.data_ptr(), B, theta.stride(0), out.data_ptr(),
+                                      _stream(stream)))
     return out
 
 

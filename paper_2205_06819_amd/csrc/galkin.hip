@@ -41,6 +41,22 @@ __global__ void __launch_bounds__(256) leapfrog_kernel(double* theta, double* mo
     if (stage != 2) theta[o] += eps * inv_mass[k] * p;
 }
 
+// Zero n counters (a kernel rather than a memset, so that callers may capture
+// the enqueueing call in a HIP graph).
+__global__ void __launch_bounds__(256) zero_u32_kernel(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Scratch of the allocation-free entry point (loglike_batch_noalloc): the
+// band partials and tickets of its launch live here instead of in the grid's
+// workspace.  Each device that loads the library holds its own copy until the
+// process ends.  Host code never passes this name to a kernel or a copy: it
+// uses the device address that hipGetSymbolAddress returns (per device, at
+// grid creation; see scratch_ptr).
+constexpr size_t SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
 }  // namespace gk
 
 // ============================================================================
@@ -539,16 +555,46 @@ int n_params(gk_grid_t g) {
     return g->P;
 }
 
+// Device address of `scratch` on the given device (which must be current),
+// looked up once per device and kept.
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[SCRATCH_MAX_DEVICES];
+
+static int scratch_ptr(int device, void** out) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES)
+        return fail(GK_EINVAL, "device %d beyond the %d devices the scratch table covers", device,
+                    SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(gk::scratch));
+        if (e != hipSuccess || !p)
+            return fail(GK_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return GK_OK;
+}
+
 int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
     int rc = valid_desc(desc);
     if (rc) return rc;
     if (!out) return fail(GK_EINVAL, "out is NULL");
     if (max_batch < 1 || max_batch > (1 << 20)) return fail(GK_EINVAL, "max_batch must be in [1, 2^20]");
     *out = nullptr;
+    int device = 0;
+    HIPCHECK(hipGetDevice(&device));
+    {
+        // set-up of the allocation-free entry point's scratch on this device
+        void* sp = nullptr;
+        rc = scratch_ptr(device, &sp);
+        if (rc) return rc;
+    }
     gk_grid* g = new gk_grid();
     g->d = *desc;
     g->max_batch = max_batch;
-    HIPCHECK(hipGetDevice(&g->device));
+    g->device = device;
     const int s = desc->supersample;
     const double sig = desc->psf_sigma_px * s;             // stencil sigma in lattice units
     const double rad2 = 9.0 * sig * sig;
@@ -861,6 +907,49 @@ int loglike_batch(gk_grid_t g, const double* theta, int B, int stride, double* l
     if (!g->has_data) return fail(GK_ESTATE, "loglike_batch before set_data");
     if (B == 0) return GK_OK;
     return run_loglike(g, theta, B, stride, logL, 0, (hipStream_t)stream);
+}
+
+int loglike_batch_noalloc(gk_grid_t g, const double* theta, int B, int stride, double* logL, void* stream) {
+    int rc = check_call(g, theta, B, stride, logL);
+    if (rc) return rc;
+    if (!g->has_data) return fail(GK_ESTATE, "loglike_batch_noalloc before set_data");
+    if (B == 0) return GK_OK;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) return fail(GK_EHIP, "hipGetDevice failed");
+    if (device != g->device) return fail(GK_EINVAL, "grid lives on device %d, current device is %d", g->device, device);
+    void* base = nullptr;
+    rc = scratch_ptr(device, &base);
+    if (rc) return rc;
+    int bh, bw, steps;
+    choose_rule(g, B, bh, bw, steps);
+    LaunchCfg c;
+    rc = make_cfg(g, bh, bw, c, 0, steps);
+    if (rc) return rc;
+    // [B] tickets, then [B][nbands] FP64 band partials
+    const size_t cnt_bytes = ((size_t)B * sizeof(unsigned) + 255) & ~(size_t)255;
+    const size_t need = c.nbands > 1 ? cnt_bytes + (size_t)B * c.nbands * sizeof(double) : 0;
+    if (need > SCRATCH_BYTES)
+        return fail(GK_EINVAL,
+                    "loglike_batch_noalloc: %d vectors x %d bands need %zu bytes of scratch (limit %zu: "
+                    "B x (8 bands + 4) bytes); use a smaller batch or wider bands (set_launch_shape)",
+                    B, c.nbands, need, SCRATCH_BYTES);
+    hipStream_t st = (hipStream_t)stream;
+    FwdArgs a;
+    fill_args(g, c, a, theta, stride);
+    a.logL = logL;
+    a.counters = (unsigned*)base;
+    a.partials = (double*)((char*)base + cnt_bytes);
+    a.pstride = c.nbands;
+    if (c.nbands > 1) {
+        // the tickets must start at zero; the previous call on this device left
+        // them zero unless it was interrupted, so clear them anyway
+        hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, a.counters, B);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(GK_EHIP, "scratch clear failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = enqueue_fwd<MODE_LOGL>(g, c, a, B, st);
+    if (e != hipSuccess) return fail(GK_EHIP, "forward launch failed: %s", hipGetErrorString(e));
+    return GK_OK;
 }
 
 int eval_maps(gk_grid_t g, const double* theta, int B, int stride, float* maps, void* stream) {
