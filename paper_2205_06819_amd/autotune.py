@@ -2,8 +2,13 @@
 
 For a grid and a batch size, times a few band shapes (pixel rows x columns
 per workgroup) of the forward kernel with HIP events on the current stream
-and installs the fastest with ``set_launch_shape``.  Results are cached in a
-JSON file keyed by the grid geometry, component set and batch size.
+and installs the fastest with ``set_launch_shape`` (``tune``); likewise for
+the gradient's adjoint kernel (``tune_adjoint``, ``set_adjoint_shape``) and
+for the band policy of a many-grid launch (``tune_multi``).  The library's
+own shape is always one of the candidates, so tuning never installs a slower
+one.  Results of ``tune`` are cached in a JSON file keyed by everything that
+changes the kernel's work: grid geometry, lattice, PSF and its mode, the
+component set, the centre frame and the batch size.
 """
 from __future__ import annotations
 
@@ -23,22 +28,21 @@ CACHE = os.environ.get("GALKIN_TUNE_CACHE",
 def _key(grid: Grid, B: int) -> str:
     s = grid.spec
     return (f"{s.nx}x{s.ny}/s{s.supersample}/sig{float(s.psf_sigma_px):.5f}/"
-            f"b{s.bulge}d{s.n_discs}h{s.halo}/B{B}")
+            f"b{s.bulge}d{s.n_discs}h{s.halo}/psf{int(getattr(s, 'psf_mode', 0))}/"
+            f"frame{float(getattr(s, 'frame_px_kpc', 0.0)):.6g},{float(getattr(s, 'frame_dx', 0.0)):.6g},"
+            f"{float(getattr(s, 'frame_dy', 0.0)):.6g}/B{B}")
 
 
-def candidates(nx: int, ny: int, B: int, n_cu: int = 256) -> List[Tuple[int, int]]:
+def candidates(nx: int, ny: int, B: int) -> List[Tuple[int, int]]:
+    """Band shapes (rows, columns) tried by tune: whole, half and fixed-size
+    splits, at most 1024 bands."""
     out = set()
     widths = sorted({nx, (nx + 1) // 2, min(nx, 64), min(nx, 32), min(nx, 16)})
     heights = sorted({ny, (ny + 1) // 2, min(ny, 32), min(ny, 16), min(ny, 8), min(ny, 4)})
     for w in widths:
         for h in heights:
-            nb = math.ceil(nx / w) * math.ceil(ny / h)
-            if nb > 1024:
-                continue
-            # enough workgroups to fill the chip, not far more bands than needed
-            if B * nb < n_cu and nb < 1024:
-                pass
-            out.add((h, w))
+            if math.ceil(nx / w) * math.ceil(ny / h) <= 1024:
+                out.add((h, w))
     return sorted(out)
 
 
@@ -70,8 +74,11 @@ def tune(grid: Grid, th: torch.Tensor, reps: int = 3, use_cache: bool = True,
             cache = {}
     if use_cache and key in cache and len(cache[key]) == 4:
         h, w, st, ms = cache[key]
-        grid.set_launch_shape(B, h, w, st)
-        return h, w, st, ms
+        try:
+            grid.set_launch_shape(B, h, w, st)
+            return h, w, st, ms
+        except GalkinError:
+            pass            # a shape this build rejects (e.g. a stale cache): tune again
     out = torch.empty(B, dtype=torch.float64, device=th.device)
     # the library's own shape for this batch size is a candidate too, so the
     # result is never slower than not tuning
@@ -146,8 +153,60 @@ def tune_multi(grids: List[Grid], th: torch.Tensor, offsets, reps: int = 3) -> T
             ms = e0.elapsed_time(e1) / reps
             if best is None or ms < best[2]:
                 best = (pol, st, ms)
+    if best is None:
+        raise GalkinError(-1, "no band policy fits every grid of this catalogue")
     pol, st, ms = best
     for g, r in zip(grids, rows):
         h, w = multi_policies(g.nx, g.ny)[pol]
         g.set_launch_shape(max(1, r), h, w, st)
     return best
+
+
+def adjoint_candidates(nx: int, ny: int) -> List[Tuple[int, int, int]]:
+    """Adjoint shapes (rows, columns, lattice rows per phase; 0 = automatic)
+    tried by tune_adjoint: columns split evenly into bands of at most 80, 64,
+    40 or 32 pixels, bands of at most 64 or 128 rows."""
+    def split(n, m):
+        k = (n + m - 1) // m
+        return (n + k - 1) // k
+    out = set()
+    for wmax in (80, 64, 40, 32):
+        for hmax in (64, 128):
+            for rows in (0, 2, 3, 4):
+                out.add((split(ny, hmax), split(nx, wmax), rows))
+    return sorted(out)
+
+
+def tune_adjoint(grid: Grid, th: torch.Tensor, reps: int = 2,
+                 shapes: Optional[List[Tuple[int, int, int]]] = None) -> Tuple[int, int, int, float]:
+    """Pick the fastest adjoint shape for gradients of batches like th by
+    timing loglike_grad_batch, and install it (set_adjoint_shape).  The
+    library's current shape is a candidate.  Returns (band_h, band_w, rows, ms)."""
+    B = th.shape[0]
+    out = torch.empty(B, dtype=torch.float64, device=th.device)
+    gbuf = torch.empty(B, th.shape[1], dtype=torch.float64, device=th.device)
+
+    def timed_grad():
+        grid.loglike_grad(th, out, gbuf)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            grid.loglike_grad(th, out, gbuf)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    h0, w0, r0 = grid.adjoint_shape()
+    best = (timed_grad(), h0, w0, r0)
+    for (h, w, r) in (shapes or adjoint_candidates(grid.nx, grid.ny)):
+        try:
+            grid.set_adjoint_shape(h, w, r)
+        except GalkinError:
+            continue
+        ms = timed_grad()
+        if ms < best[0]:
+            best = (ms, *grid.adjoint_shape())
+    ms, h, w, r = best
+    grid.set_adjoint_shape(h, w, r)
+    return h, w, r, ms

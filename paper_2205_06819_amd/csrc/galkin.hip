@@ -403,7 +403,7 @@ static void fill_args(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, const do
     a.ivar = g->d_ivar;
     a.span = g->d_span;
     a.logdet = g->d_logdet;
-    a.pstride = MAX_BANDS;
+    a.pstride = c.nbands;          // partials packed per vector: [B][nbands]
     a.band_h = c.band_h;
     a.band_w = c.band_w;
     a.nbx = c.nbx;
@@ -740,7 +740,11 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
         static const int tpads[] = {4, 6, 9, 12, 16, 20, 25};
         g->tpad = 0;
         for (int t : tpads)
-            if (t >= pad) { g->tpad = t; break; }
+            if (t >= pad && lag_cap(t) >= D) { g->tpad = t; break; }
+        if (!g->tpad) {
+            free_grid(g);
+            return fail(GK_EINVAL, "no compiled stencil for pad = %d and lag %d", pad, D);
+        }
     }
     std::vector<float> gw64(std::max(pad + 1, 64), 0.0f);
     std::copy(gw.begin(), gw.end(), gw64.begin());

@@ -197,12 +197,22 @@ __device__ __forceinline__ float horner8d(const float4 a, const float4 b, float 
     return p;
 }
 
+// Value and derivative of a polynomial written as a Horner expression: the
+// tail macros below evaluated on Dual arguments give P(w) and P'(w) exactly
+// (forward-mode differentiation of the expression).
+struct Dual {
+    float v, d;
+};
+__device__ __forceinline__ Dual operator+(float a, Dual b) { return Dual{a + b.v, b.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, float b) { return Dual{a.v * b, a.d * b}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual{a.v * b.v, fmaf(a.d, b.v, a.v * b.d)}; }
+
 // bulge g(s), h(s) for s >= 1e-6 from the staged table (Hernquist, or Jaffe
 // when JF); beyond the table s^3 g and s^4 h are cubics in w = 1/s
-template <bool JF>
-__device__ __forceinline__ float tail_g(float w) { return JF ? GK_TAIL_JG(w) : GK_TAIL_G(w); }
-template <bool JF>
-__device__ __forceinline__ float tail_h(float w) { return JF ? GK_TAIL_JH(w) : GK_TAIL_H(w); }
+template <bool JF, typename T>
+__device__ __forceinline__ T tail_g(T w) { return JF ? GK_TAIL_JG(w) : GK_TAIL_G(w); }
+template <bool JF, typename T>
+__device__ __forceinline__ T tail_h(T w) { return JF ? GK_TAIL_JH(w) : GK_TAIL_H(w); }
 
 template <bool JF>
 __device__ __forceinline__ void eval_gh(const float4* __restrict__ T, float s, float& g, float& h) {
@@ -231,14 +241,12 @@ __device__ __forceinline__ void eval_gh_d(const float4* __restrict__ T, float s,
     } else {
         // s^3 g = Pg(w), s^4 h = Ph(w), w = 1/s: dg/ds = -w^4 (3 Pg + w Pg'), dh/ds = -w^5 (4 Ph + w Ph')
         const float w = frcp(s), w2 = w * w, w3 = w2 * w;
-        const float pg = tail_g<JF>(w), ph = tail_h<JF>(w);
-        const float e = 1.0e-3f;                           // tails are cubics; exact slope
-        const float pg1 = (tail_g<JF>(w + e) - tail_g<JF>(w - e)) / (2.0f * e);
-        const float ph1 = (tail_h<JF>(w + e) - tail_h<JF>(w - e)) / (2.0f * e);
-        g = w3 * pg;
-        h = w3 * w * ph;
-        dg = -w3 * w * (3.0f * pg + w * pg1);
-        dh = -w3 * w2 * (4.0f * ph + w * ph1);
+        const Dual W{w, 1.0f};
+        const Dual pg = tail_g<JF>(W), ph = tail_h<JF>(W);     // cubics and their exact slopes
+        g = w3 * pg.v;
+        h = w3 * w * ph.v;
+        dg = -w3 * w * (3.0f * pg.v + w * pg.d);
+        dh = -w3 * w2 * (4.0f * ph.v + w * ph.d);
     }
 }
 
@@ -263,10 +271,10 @@ __device__ __forceinline__ float eval_phi_d(const float4* __restrict__ T, float 
         return v;
     }
     const float w = frcp(y);
-    const float e = 1.0e-4f;
-    const float p = GK_TAIL_PHI(w), p1 = (GK_TAIL_PHI(w + e) - GK_TAIL_PHI(w - e)) / (2.0f * e);
-    d = -0.25f * w * w * (p + w * p1);
-    return 0.25f * w * p;
+    const Dual W{w, 1.0f};
+    const Dual p = GK_TAIL_PHI(W);                     // 4 y phi = P(w): value and exact slope
+    d = -0.25f * w * w * (p.v + w * p.d);
+    return 0.25f * w * p.v;
 }
 
 // NFW m(x) = [ln(1+x) - x/(1+x)] / x

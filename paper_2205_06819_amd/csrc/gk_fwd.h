@@ -50,17 +50,19 @@ typedef const __attribute__((address_space(4))) int* const_int_ptr;
 // H_0..H_PAD at the pixel centre from one batch of LDS loads; the pixel row
 // at lag d (d steps back) takes weight g(|b|) times H_A(|b|), b = d s + ph - pad.
 // acc[d] holds the running PSF sum of the pixel row d steps back; it is
-// shifted by one each step, so acc[D] is complete after this call.
-template <int PAD>
+// shifted by one each step, so acc[D] is complete after this call.  DL is the
+// largest lag the tap count PAD admits (lag_cap): the loop over lags stops
+// there instead of at DMAX.
+template <int PAD, int DL>
 __device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rstride, int s,
                                             const float* __restrict__ gw, const int2* __restrict__ tab,
                                             float (&acc)[DMAX + 1]) {
     float g[PAD + 1];
 #pragma unroll
     for (int k = 0; k <= PAD; ++k) g[k] = gw[k];
-    float con[DMAX + 1];
+    float con[DL + 1];
 #pragma unroll
-    for (int d = 0; d <= DMAX; ++d) con[d] = 0.0f;
+    for (int d = 0; d <= DL; ++d) con[d] = 0.0f;
     for (int ph = 0; ph < s; ++ph) {
         const float* L = L0 + ph * rstride;
         float H[PAD + 1];
@@ -71,14 +73,14 @@ __device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rs
         // beyond D have weight 0, so the loop has a fixed trip count
         const_int_ptr t = (const_int_ptr)tab + 2 * ph * DSTRIDE;
 #pragma unroll
-        for (int d = 0; d <= DMAX; ++d) {
+        for (int d = 0; d <= DL; ++d) {
             const int A = t[2 * d];
             const float w = __int_as_float(t[2 * d + 1]);
             con[d] = fmaf(w, H[A], con[d]);
         }
     }
 #pragma unroll
-    for (int d = DMAX; d >= 1; --d) acc[d] = acc[d - 1] + con[d];
+    for (int d = DL; d >= 1; --d) acc[d] = acc[d - 1] + con[d];
     acc[0] = con[0];
 }
 
@@ -248,7 +250,7 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
                 const int q = q0 + k;
                 if (q >= Q) break;
                 const float* L0 = s_rows + (k * s) * 4 * XW + pm * XW + pc * s + pad;
-#define GK_SUB(PADV) stencil_sub<PADV>(L0, 4 * XW, s, a.gw, a.tab, acc)
+#define GK_SUB(PADV) stencil_sub<PADV, lag_cap(PADV)>(L0, 4 * XW, s, a.gw, a.tab, acc)
                 if ((a.map_mask >> pm) & 1) {       // maps without valid pixels stay zero
                     switch (a.tpad) {
                         case 4: GK_SUB(4); break;

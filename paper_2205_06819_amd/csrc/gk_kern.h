@@ -26,7 +26,7 @@ struct FwdArgs {
     const int2* span;       // [ny] first / last column valid in any map
     const double* logdet;   // sum of ln(2 pi e^2) over valid pixels (device scalar)
     int band_h, band_w, nbx, nbands;
-    int pstride;            // row stride of partials (>= nbands)
+    int pstride;            // row stride of partials (= nbands: one FP64 partial per band of a vector)
     int gsub;               // pixel-row steps per model phase (gsub * s <= RS_CAP lattice rows)
     int xw;                 // row stride of the row buffer (floats)
     int tpad;               // compile-time tap count used by the stencil (>= pad)
@@ -43,6 +43,14 @@ struct FwdArgs {
 
 constexpr int DMAX = 10;        // largest lag D = floor(2 pad / s) supported
 constexpr int DSTRIDE = DMAX + 1;
+
+// The forward stencil is compiled for a few tap counts (the smallest one >=
+// pad is used).  For each, the largest lag D = floor(2 pad / s) that a grid
+// accepted by create_grid (D <= DMAX) can have with that tap count: s = 1 only
+// fits pad <= 5 (tap counts 4 and 6), s = 3 fits pad <= 16 and s >= 5 the rest.
+__host__ __device__ constexpr int lag_cap(int tpad) {
+    return tpad == 4 ? 8 : tpad == 6 ? 10 : tpad == 9 ? 6 : tpad == 12 ? 8 : tpad == 16 ? 10 : tpad == 20 ? 8 : 10;
+}
 constexpr int RS_CAP = 16;      // lattice rows per model phase
 constexpr int GSUB_CAP = 4;     // pixel-row steps per model phase
 

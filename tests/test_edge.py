@@ -14,7 +14,7 @@ from oracle import model as M
 
 pytestmark = pytest.mark.gpu
 
-MAP_RTOL, LOGL_ATOL, MAP_EPS = 1e-4, 1e-3, 1e-5
+from bounds import LOGL_ATOL, MAP_RTOL, logl_tol
 GRAD_RTOL, GRAD_NORM_TOL = 1e-3, 1e-4
 
 
@@ -32,14 +32,7 @@ def gk():
 
 
 def bound(spec, data, err, th):
-    F = M.psf_maps(spec, th)
-    F = np.stack([F[0], F[1], F[2], 1.0 / F[3]])
-    ok = M.valid_masks(data, err)
-    tot = 0.0
-    for m in range(4):
-        r = (F[m][ok[m]] - data[m][ok[m]]) / err[m][ok[m]]
-        tot += np.sum(np.abs(r) * np.abs(F[m][ok[m]]) / err[m][ok[m]])
-    return LOGL_ATOL + MAP_EPS * tot
+    return logl_tol(spec, data, err, th, "far")
 
 
 def check_grad(got, ref, tag):
@@ -124,3 +117,45 @@ def test_psf_beyond_the_limits_is_rejected(gk):
         desc = gk.make_desc(spec)
         assert gk._lib.create_grid(ctypes.byref(desc), 2, ctypes.byref(h)) == gk.GK_EINVAL
         assert "PSF too wide" in gk.last_error()
+
+
+@pytest.mark.parametrize("bulge", [W.BULGE_HERNQUIST, W.BULGE_JAFFE])
+def test_tail_branches(gk, bulge):
+    """A bulge of R_b = 5e-4 kpc and a disc of R_d = 1e-3 kpc on a 0.3 kpc/px
+    grid: the lattice reaches s = R / R_b > 4096 and y = r / (2 R_d) > 1024, so
+    the special functions run on their large-argument tails (cubics in 1/s and
+    1/y whose slopes the adjoint takes analytically)."""
+    spec = W.GridSpec(24, 20, 0.3, 3, 1.0, bulge, 1, W.HALO_NFW)
+    names = W.param_names(spec)
+    rng = np.random.default_rng(zlib.crc32(f"tails-{bulge}".encode()))
+    truth = W.draw_thetas(spec, 1, rng)[0]
+    truth[names.index("logMb")], truth[names.index("Rb")] = 9.0, 5e-4
+    truth[names.index("Rd1")] = 1e-3
+    # largest s and y on the lattice: every point is >= 0.3/3 kpc from the centre
+    # only near it, the far corners are ~3.6 kpc out
+    rmax = 0.3 * np.hypot(12, 10)
+    assert rmax / 5e-4 > 4096 and rmax / (2 * 1e-3) > 1024
+    data, err = M.synthetic_data(spec, truth, np.ones((spec.ny, spec.nx), bool), rng)
+    other = truth.copy()
+    other[names.index("incl")] += 3.0
+    other[names.index("Rb")] = 8e-4
+    thetas = np.vstack([truth[None], other[None]])
+    say(f"[edge] tails, bulge kind {bulge}")
+    grid = gk.Grid(spec, max_batch=4)
+    grid.set_data(data, err)
+    th = torch.tensor(thetas, device="cuda")
+    maps = grid.maps(th).cpu().numpy().astype(np.float64)
+    logl = grid.loglike(th).cpu().numpy()
+    _, g = grid.loglike_grad(th)
+    g = g.cpu().numpy()
+    for k, t in enumerate(thetas):
+        F = M.psf_maps(spec, t)
+        ref = np.stack([F[0], F[1], F[2], 1.0 / F[3]])
+        for m in (0, 2, 3):
+            assert np.max(np.abs(maps[k, m] / ref[m] - 1.0)) < MAP_RTOL, (k, m)
+        assert np.max(np.abs(maps[k, 1] - ref[1])) <= MAP_RTOL * np.max(np.abs(ref[1])) + 1e-6
+        lo = M.loglike(spec, data, err, t)
+        tol = LOGL_ATOL if k == 0 else bound(spec, data, err, t)
+        assert abs(logl[k] - lo) <= tol, (k, logl[k], lo)
+        check_grad(g[k], M.grad_complex_step(spec, data, err, t), f"tails[{k}]")
+    grid.close()

@@ -14,7 +14,7 @@ from oracle import model as M
 
 pytestmark = pytest.mark.gpu
 
-LOGL_ATOL, MAP_EPS = 1e-3, 1e-5
+from bounds import LOGL_ATOL, residual_stats
 GRAD_RTOL, GRAD_NORM_TOL = 1e-3, 1e-4
 
 
@@ -32,15 +32,8 @@ def gk():
 
 
 def logl_bound(spec, data, err, th):
-    """1e-3 plus the first-order effect of a relative map error MAP_EPS."""
-    F = M.psf_maps(spec, th)
-    F = np.stack([F[0], F[1], F[2], 1.0 / F[3]])
-    ok = M.valid_masks(data, err)
-    tot = 0.0
-    for m in range(4):
-        r = (F[m][ok[m]] - data[m][ok[m]]) / err[m][ok[m]]
-        tot += np.sum(np.abs(r) * np.abs(F[m][ok[m]]) / err[m][ok[m]])
-    return MAP_EPS * tot
+    """The first-order effect of the worst relative map error (tests/bounds.py)."""
+    return residual_stats(spec, data, err, th)[1]
 
 
 def check_grad(got, ref, tag):
