@@ -86,15 +86,25 @@ typedef struct {
     double frame_dy;       /* this grid's centre (0, 0 when they coincide)     */
 } gk_grid_desc;
 
-/* Create a grid handle on the current HIP device.  Allocates every device
- * buffer the hot-path calls need for batches of up to max_batch vectors
- * (>= 1), so those calls never allocate.  *out receives the handle. */
+/* Create a grid handle on the current HIP device: the pixel grid and its
+ * model lattice (Sec. 2.1; Appendix A's sub-grid), the PSF stencil (Sec. 3.1)
+ * and the component set (Sec. 2.2-2.3).  Uploads the stencil tables and
+ * allocates every device buffer the hot-path calls need for batches of up to
+ * max_batch vectors (>= 1), so those calls never allocate (Appendix A:
+ * allocate once, transfer once).  The gradient's pixel-adjoint buffer is
+ * capped at ~2 GiB (larger gradient batches run in chunks).  *out receives
+ * the handle; GK_EINVAL for an invalid descriptor or a PSF wider than this
+ * build supports (3 sigma s <= 25 lattice points, floor(2 pad / s) <= 10),
+ * GK_ENOMEM / GK_EHIP when the device refuses. */
 int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out);
 
-/* Release a grid handle and its device memory (synchronises the device). */
+/* Release a grid handle and its device memory (synchronises the device);
+ * cached many-grid plans that use it are dropped. */
 int destroy_grid(gk_grid_t grid);
 
-/* Number of model parameters P of the grid's component set. */
+/* Number of model parameters P of the grid's component set (the layout at
+ * the top of this file; 17 for bulge + two discs + halo, as in the paper's
+ * Table 1), or GK_EINVAL for a NULL grid. */
 int n_params(gk_grid_t grid);
 
 /* Upload the observed maps (Sec. 2.5.1): value and err are float32
@@ -110,11 +120,16 @@ int n_params(gk_grid_t grid);
 int set_data(gk_grid_t grid, const float* value, const float* err, int on_device,
              void* hip_stream);
 
-/* logL[b] = sum over the four maps and their valid pixels of
+/* The Gaussian log-likelihood of Sec. 2.5.1 (likelihood equation) for each
+ * parameter vector:
+ *   logL[b] = sum over the four maps and their valid pixels of
  *   -1/2 [ (F_m(p) - d_m(p))^2 / e_m(p)^2 + ln(2 pi e_m(p)^2) ],
- * with F the PSF-averaged model (the model M/L map is 1 / <L/M>), for
- * b in [0, B).  theta: device float64 [B][stride]; logL: device float64 [B].
- * B may be 0 (nothing is enqueued); B <= max_batch. */
+ * with F the model of Sec. 2.1-2.4 (surface brightness, light-weighted
+ * velocity and dispersion, <L/M>) averaged over the PSF (Sec. 3.1; the model
+ * M/L map is 1 / <L/M>, eq:ML_ratio), for b in [0, B).  theta: device float64
+ * [B][stride]; logL: device float64 [B] (-inf for rows outside the physical
+ * domain).  B may be 0 (nothing is enqueued); B <= max_batch, else GK_EINVAL;
+ * GK_ESTATE before set_data.  One launch per call. */
 int loglike_batch(gk_grid_t grid, const double* theta, int B, int stride, double* logL,
                   void* hip_stream);
 
@@ -134,16 +149,23 @@ int loglike_batch_noalloc(gk_grid_t grid, const double* theta, int B, int stride
                           void* hip_stream);
 
 /* As loglike_batch, and also grad[b][k] = d logL[b] / d theta[b][k] for
- * k < P (columns P..stride-1 of grad are set to 0).  grad: device float64
- * [B][stride].  The gradient is the exact derivative of the FP32 model
- * (hand-written adjoint), accumulated in FP64. */
+ * k < P (columns P..stride-1 of grad are set to 0; zero rows outside the
+ * domain).  grad: device float64 [B][stride].  Not a method of the paper
+ * (which samples without gradients): the derivative of the same model
+ * (Sec. 2.1-2.4, 3.1, 2.5.1), by a hand-written adjoint — the forward
+ * launch also writes d logL / d F per pixel, a second launch applies the
+ * transposed PSF stencil and the reverse point model — exact for the FP32
+ * model up to FP32 rounding, accumulated in FP64.  Two launches per chunk of
+ * at most ~2 GiB / (16 bytes x pixels) vectors.  The log-likelihoods equal
+ * loglike_batch's bit for bit. */
 int loglike_grad_batch(gk_grid_t grid, const double* theta, int B, int stride, double* logL,
                        double* grad, void* hip_stream);
 
-/* PSF-averaged model maps at every pixel, float32 device [B][4][ny][nx]:
- * surface brightness, l.o.s. velocity, l.o.s. dispersion and M/L
- * (= 1 / PSF-averaged <L/M>).  Requires no data.  Rows outside the
- * physical domain give NaN maps. */
+/* The model maps themselves (Sec. 2.4 total brightness, velocity and
+ * dispersion equations; eq:ML_ratio) averaged over the PSF (Sec. 3.1) at
+ * every pixel, float32 device [B][4][ny][nx]: surface brightness [Lsun/pc^2],
+ * l.o.s. velocity and dispersion [km/s] and M/L (= 1 / PSF-averaged <L/M>).
+ * Requires no data.  Rows outside the physical domain give NaN maps. */
 int eval_maps(gk_grid_t grid, const double* theta, int B, int stride, float* maps,
               void* hip_stream);
 

@@ -14,6 +14,13 @@ parallel and links them into paper_2205_06819_amd/libgalkin.so:
 
 Packed FP32 instructions are disabled (``-packed-fp32-ops``); the host pass
 warns that it does not know that target feature, which is harmless.
+
+``build_sanitized_harness()`` also links tests/sanitize/abi_check.cpp against
+the host translation unit compiled with AddressSanitizer and
+UndefinedBehaviorSanitizer (host code only: each -fsanitize flag goes after
+-Xarch_host) and the kernel objects of the normal build, into
+paper_2205_06819_amd/_build/abi_check_asan (run by tests/test_sanitize.py).
+The objects are kept in paper_2205_06819_amd/_build/.
 """
 from __future__ import annotations
 
@@ -21,13 +28,16 @@ import os
 import shutil
 import subprocess
 import sys
-import tempfile
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgalkin.so")
+OBJDIR = os.path.join(HERE, "_build")
+HARNESS = os.path.join(OBJDIR, "abi_check_asan")
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
 ARCH = os.environ.get("GALKIN_ARCH", "gfx950")
 
 # (object name, source, extra defines)
@@ -62,26 +72,48 @@ def _run(cmd):
 def build(verbose: bool = False, jobs: int = 0) -> str:
     cc = hipcc()
     jobs = jobs or max(1, min(len(UNITS), os.cpu_count() or 1, 16))
-    with tempfile.TemporaryDirectory(prefix="galkin_build_") as tmp:
-        cmds = []
-        for name, src, defs in UNITS:
-            obj = os.path.join(tmp, name + ".o")
-            cmds.append([cc, *_flags(), *defs, "-c", os.path.join(CSRC, src), "-o", obj])
-        if verbose:
-            for c in cmds:
-                print(" ".join(c), file=sys.stderr)
-        with ThreadPoolExecutor(max_workers=jobs) as ex:
-            list(ex.map(_run, cmds))
-        out = LIB + ".tmp"
-        link = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}",
-                *[os.path.join(tmp, n + ".o") for n, _, _ in UNITS], "-o", out]
-        if verbose:
-            print(" ".join(link), file=sys.stderr)
-        _run(link)
-        os.replace(out, LIB)
+    os.makedirs(OBJDIR, exist_ok=True)
+    cmds = []
+    for name, src, defs in UNITS:
+        obj = os.path.join(OBJDIR, name + ".o")
+        cmds.append([cc, *_flags(), *defs, "-c", os.path.join(CSRC, src), "-o", obj])
+    if verbose:
+        for c in cmds:
+            print(" ".join(c), file=sys.stderr)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(_run, cmds))
+    out = LIB + ".tmp"
+    link = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}",
+            *[os.path.join(OBJDIR, n + ".o") for n, _, _ in UNITS], "-o", out]
+    if verbose:
+        print(" ".join(link), file=sys.stderr)
+    _run(link)
+    os.replace(out, LIB)
     return LIB
+
+
+def build_sanitized_harness(verbose: bool = False) -> str:
+    """The ABI check program with the host code under ASan/UBSan (needs the
+    kernel objects of build())."""
+    cc = hipcc()
+    kern = [os.path.join(OBJDIR, n + ".o") for n, _, _ in UNITS if n != "galkin"]
+    if not all(os.path.exists(k) for k in kern):
+        build(verbose)
+    host = os.path.join(OBJDIR, "galkin_asan.o")
+    check = os.path.join(OBJDIR, "abi_check_asan.o")
+    cmds = [[cc, *_flags(), "-O1", "-g", *SAN, "-c", os.path.join(CSRC, "galkin.hip"), "-o", host],
+            [cc, *_flags(), "-O1", "-g", *SAN, "-c", os.path.join(ROOT, "tests", "sanitize", "abi_check.cpp"),
+             "-o", check]]
+    with ThreadPoolExecutor(max_workers=2) as ex:
+        list(ex.map(_run, cmds))
+    out = HARNESS + ".tmp"
+    _run([cc, f"--offload-arch={ARCH}", *SAN, check, host, *kern, "-o", out])
+    os.replace(out, HARNESS)
+    return HARNESS
 
 
 if __name__ == "__main__":
     path = build(verbose="-v" in sys.argv)
     print(path)
+    if "--harness" in sys.argv:
+        print(build_sanitized_harness(verbose="-v" in sys.argv))
