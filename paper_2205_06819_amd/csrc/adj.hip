@@ -121,8 +121,6 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     const int4* s_ht = (const int4*)(smem + L.ht);  // [s][s][KP2]
     const int2* s_vt = (const int2*)(smem + L.vt);  // [s][DSTRIDE]
     double* s_red = (double*)(smem + L.red);
-    int* s_lo = (int*)(smem + L.lo);
-    int* s_hi = (int*)(smem + L.hi);
     int2* s_span = (int2*)(smem + L.span);
     int* s_aof = (int*)(smem + L.aof);
     int* s_plo = (int*)(smem + L.plo);
@@ -154,39 +152,30 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
         for (int i = tid; i <= pad; i += BS) s_aof[i] = a.aof[i];
     }
     __syncthreads();
-    // needed lattice columns of each lattice row: the union of the stencils of
-    // the band's valid pixels (elsewhere every pixel adjoint in reach is zero)
-    for (int r = tid; r < NFR; r += BS) {
-        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
-        const int jhi = min(NR - 1, r / s);
-        int lo = 1 << 30, hi = -(1 << 30);
-        for (int jj = jlo; jj <= jhi; ++jj) {
-            int bb = r - jj * s - pad;
-            bb = bb < 0 ? -bb : bb;
-            const int2 sp = s_span[jj];
-            const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
-            if (cl <= ch) {
-                const int A = s_aof[bb];
-                lo = min(lo, cl * s + hs + pad - A);
-                hi = max(hi, ch * s + hs + pad + A);
-            }
-        }
-        s_lo[r] = hi >= lo ? lo - ubase : (1 << 30);
-        s_hi[r] = hi >= lo ? hi - ubase : -(1 << 30);
-    }
-    __syncthreads();
+    // needed lattice columns of each phase: the union, over the phase's lattice
+    // rows, of the stencils of the band's valid pixels (elsewhere every pixel
+    // adjoint in reach is zero)
     const int nph = (NFR + RS - 1) / RS;
     for (int k = tid; k < nph; k += BS) {
         int lo = 1 << 30, hi = -(1 << 30);
         for (int r = k * RS; r < min(NFR, (k + 1) * RS); ++r) {
-            lo = min(lo, s_lo[r]);
-            hi = max(hi, s_hi[r]);
+            const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
+            const int jhi = min(NR - 1, r / s);
+            for (int jj = jlo; jj <= jhi; ++jj) {
+                int bb = r - jj * s - pad;
+                bb = bb < 0 ? -bb : bb;
+                const int2 sp = s_span[jj];
+                const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
+                if (cl <= ch) {
+                    const int A = s_aof[bb];
+                    lo = min(lo, cl * s + hs + pad - A);
+                    hi = max(hi, ch * s + hs + pad + A);
+                }
+            }
         }
-        s_plo[k] = hi >= lo ? lo : 0;
+        s_plo[k] = hi >= lo ? lo - ubase : 0;
         s_pw[k] = hi >= lo ? hi - lo + 1 : 0;
     }
-    __syncthreads();
-
     const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
                  (const float4*)(s_tab + TAB_GH + TAB_PHI)};
     float ad[NCONST];
@@ -197,15 +186,15 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     const float inv_nc = 1.0f / (float)NC;
     const size_t mstr = (size_t)G.ny * G.nx;
     const float* fb = a.fbar + (size_t)b * 4 * mstr;
+    // Pixel rows of rbar enter a ring of RB rows, slot = row mod RB.  The rows
+    // a phase reaches are loaded during the previous phase's gather (the ring
+    // is not read then), so a phase needs two barriers.
     int loaded = -1;                                // last pixel row put in the ring
-    for (int rA = 0, ph_i = 0; rA < NFR; rA += RS, ++ph_i) {
-        const int nrow = min(RS, NFR - rA);
-        // pixel rows [qlo - D, qhi] are in reach of lattice rows [rA, rA + nrow); ring
-        // slot of pixel row jj: base + jj - (qlo - D), wrapped, base = (qlo - D) mod RB
-        const int qlo = rA / s, qhi = (rA + nrow - 1) / s;
-        const int base = ((qlo - D) % RB + RB) % RB;
-        // ---- the phase's new pixel rows (loaded + 1 .. qhi; zeros past the band)
-        const int nnew = qhi - loaded;
+    auto load_rows = [&](int rA_next) {
+        const int nrow_n = min(RS, NFR - rA_next);
+        const int qlo_n = rA_next / s, qhi_n = (rA_next + nrow_n - 1) / s;
+        const int base_n = ((qlo_n - D) % RB + RB) % RB;
+        const int nnew = qhi_n - loaded;
         for (int p = tid; p < nnew * NC; p += BS) {
             const int k = (int)(((float)p + 0.5f) * inv_nc), cc = p - k * NC;
             const int jj = loaded + 1 + k;
@@ -214,12 +203,20 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
                 const size_t pix = (size_t)(j0 + jj) * G.nx + c0 + cc;
                 v = make_float4(fb[pix], fb[mstr + pix], fb[2 * mstr + pix], fb[3 * mstr + pix]);
             }
-            int slot = base + jj - (qlo - D);
+            int slot = base_n + jj - (qlo_n - D);
             slot = slot >= RB ? slot - RB : slot;
             s_ring[slot * NC + cc] = v;
         }
-        loaded = qhi;
-        __syncthreads();
+        loaded = max(loaded, qhi_n);
+    };
+    load_rows(0);
+    __syncthreads();
+    for (int rA = 0, ph_i = 0; rA < NFR; rA += RS, ++ph_i) {
+        const int nrow = min(RS, NFR - rA);
+        // pixel rows [qlo - D, qhi] are in reach of lattice rows [rA, rA + nrow); ring
+        // slot of pixel row jj: base + jj - (qlo - D), wrapped, base = (qlo - D) mod RB
+        const int qlo = rA / s;
+        const int base = ((qlo - D) % RB + RB) % RB;
         // ---- vertical pass: group sums per (lattice row, pixel column)
         for (int p = tid; p < nrow * NC; p += BS) {
             const int rl = (int)(((float)p + 0.5f) * inv_nc), cc = p - rl * NC;
@@ -281,6 +278,7 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             }
             point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
         }
+        if (rA + RS < NFR) load_rows(rA + RS);      // the next phase's new pixel rows
         __syncthreads();
     }
 

@@ -280,18 +280,54 @@ static int set_adj_shape(gk_grid* g, int bh, int bw, int rows) {
 }
 
 // Default adjoint shape (measured on the 80 x 80, 100 x 100 and 300 x 300
-// benchmark grids): the widest band (columns split evenly, at most 80) whose
-// phases keep >= 90 % of the threads busy with at least two lattice rows per
-// phase, within the LDS that leaves room for three workgroups per CU; rows
-// per phase: the best fill, then the fewest rows (a larger row buffer costs
-// occupancy).  Bands are up to 64 rows tall, taller when the grid would need
-// more than MAX_BANDS_ADJ bands.  A grid whose adjoint fits no shape keeps
+// benchmark grids): bands as tall as possible (up to 128 rows: each band
+// recomputes a lattice halo of 2 pad rows) and as wide as possible (columns
+// split evenly, at most 80, at least 32 while a wider shape is sought) while
+// a vector still spans at least two bands (more workgroups), with 2 to 4
+// lattice rows per phase: the fewest that reach the best thread fill, which
+// must be >= 90 %, within the LDS that leaves room for three workgroups per
+// CU.  (More rows per phase enlarge the ring and the group sums and measured
+// slower at equal fill.)  Bands grow taller when the grid would need more
+// than MAX_BANDS_ADJ bands.  A grid whose adjoint fits no shape keeps
 // adj_nbands = 0: its forward calls work and its gradient calls return
 // GK_EINVAL.
 static int default_adj_shape(gk_grid* g) {
     const int nx = g->d.nx, ny = g->d.ny, s = g->geo.s, pad = g->geo.pad;
     const std::string saved = g_err;
     auto split = [](int n, int m) { const int k = (n + m - 1) / m; return (n + k - 1) / k; };
+    const bool big = nx >= 40 || ny >= 40;          // room for two bands
+    for (int cap : {ADJ_LDS_3, ADJ_LDS_MAX})
+        for (int pass = 0; pass < 2; ++pass)        // pass 1: single-band shapes allowed
+            for (int hmax : {128, 64, 256, 512, 1024, 2048, 4096}) {
+                const int bh = split(ny, hmax);
+                int bbw = 0, brows = 0;
+                for (int wmax : {80, 64, 40, 32, 20, 16, 8}) {
+                    if (pass == 0 && wmax < 32) break;
+                    const int bw = split(nx, wmax);
+                    const int nb = ((nx + bw - 1) / bw) * ((ny + bh - 1) / bh);
+                    if (nb > MAX_BANDS_ADJ || (pass == 0 && big && nb < 2)) continue;
+                    int rows = 0;
+                    double fill = -1.0;
+                    for (int r = 2; r <= 4; ++r) {
+                        if (adj_lds_of(g, bh, bw, r) > cap) break;
+                        const double f = adj_fill(s, pad, bw, r);
+                        if (f > fill + 1e-9) {
+                            fill = f;
+                            rows = r;
+                        }
+                    }
+                    if (rows && fill >= 0.9) {
+                        bbw = bw;
+                        brows = rows;
+                        break;
+                    }
+                }
+                if (bbw && set_adj_shape(g, bh, bbw, brows) == GK_OK) {
+                    g_err = saved;
+                    return GK_OK;
+                }
+            }
+    // nothing reached the fill target: the best fill of the default heights
     for (int cap : {ADJ_LDS_3, ADJ_LDS_MAX})
         for (int hmax = 64; hmax <= 4096; hmax *= 2) {
             const int bh = split(ny, hmax);
@@ -300,23 +336,15 @@ static int default_adj_shape(gk_grid* g) {
             for (int wmax : {80, 64, 40, 32, 20, 16, 8}) {
                 const int bw = split(nx, wmax);
                 if (((nx + bw - 1) / bw) * ((ny + bh - 1) / bh) > MAX_BANDS_ADJ) continue;
-                int rows = 0;
-                double fill = -1.0;
-                for (int r : {2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 1}) {
-                    if (adj_lds_of(g, bh, bw, r) > cap) continue;
+                for (int r = 1; r <= RS_CAP; ++r) {
+                    if (adj_lds_of(g, bh, bw, r) > cap) break;
                     const double f = adj_fill(s, pad, bw, r);
-                    if (f > fill + 1e-9) {
-                        fill = f;
-                        rows = r;
+                    if (f > bfill + 1e-9) {
+                        bfill = f;
+                        bbw = bw;
+                        brows = r;
                     }
                 }
-                if (!rows) continue;
-                if (fill > bfill + 1e-9) {
-                    bfill = fill;
-                    bbw = bw;
-                    brows = rows;
-                }
-                if (fill >= 0.9 && rows >= 2) break;
             }
             if (bbw && set_adj_shape(g, bh, bbw, brows) == GK_OK) {
                 g_err = saved;

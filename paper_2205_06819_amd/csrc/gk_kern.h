@@ -116,7 +116,7 @@ struct AdjArgs {
 };
 
 struct AdjLayout {              // LDS carve-up of the adjoint (4-byte words), host and device
-    int tab, ring, S, vt, ht, red, lo, hi, span, aof, plo, pw, total_bytes;
+    int tab, ring, S, vt, ht, red, span, aof, plo, pw, total_bytes;
 };
 
 __host__ __device__ inline AdjLayout adj_layout(int band_h, int band_w, int s, int pad, int D, int rows, int nlev,
@@ -132,9 +132,6 @@ __host__ __device__ inline AdjLayout adj_layout(int band_h, int band_w, int s, i
     off = (off + 1) & ~1;
     L.red = off;  off += RED_SLOTS * NCONST * 2;                   // doubles
     const int nfrm = nfr_max(band_h, s, pad);
-    L.lo = off;   off += nfrm;
-    L.hi = off;   off += nfrm;
-    off = (off + 1) & ~1;
     L.span = off; off += 2 * band_h;
     L.aof = off;  off += pad + 1;
     const int nch = (nfrm + rows - 1) / rows + 1;
