@@ -44,7 +44,7 @@ ARCH = os.environ.get("GALKIN_ARCH", "gfx950")
 UNITS = [("galkin", "galkin.hip", [])]
 UNITS += [(f"fwd_m{m}_l{l}", "fwd_inst.hip", [f"-DGK_MODE={m}", f"-DGK_LW={l}"]) for m in (0, 1, 2) for l in (0, 1)]
 UNITS += [(f"multi_l{l}", "multi_inst.hip", [f"-DGK_LW={l}"]) for l in (0, 1)]
-UNITS += [(f"adj_l{l}", "adj.hip", [f"-DGK_LW={l}"]) for l in (0, 1)]
+UNITS += [(f"adj_l{l}_k{k}", "adj.hip", [f"-DGK_LW={l}", f"-DGK_KH={k}"]) for l in (0, 1) for k in (4, 6)]
 
 
 def hipcc() -> str:

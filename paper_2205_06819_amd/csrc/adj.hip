@@ -2,16 +2,19 @@
 // per-pixel adjoints rbar = d logL / d F (written by the forward kernel in its
 // adjoint-seed mode), compiled once per PSF mode (-DGK_LW=0|1).
 //
-// One workgroup = one parameter vector x one band of pixels.  The band's
-// share of the gradient is the sum, over the band's pixels p and maps m, of
-// rbar_m(p) dF_m(p)/dtheta; F_m(p) averages the model over the lattice points
-// of p's 3-sigma stencil (Sec. 3.1, PSF equation), so the share needs the
-// adjoint of every lattice point of the band's padded lattice,
-//   fbar(x, r) = (1/W) sum_p rbar(p) g(|x - x_p|) g(|r - r_p|) [inside the stencil],
-// (the transposed stencil), followed by the reverse point model.  Bands add
-// up exactly to the whole grid (each pixel belongs to one band), so the halo
-// points of neighbouring bands need no exchange.  The lattice is streamed top
-// to bottom in phases of R lattice rows (any R, independent of s):
+// One workgroup = one parameter vector x one block of the padded lattice.
+// The gradient is the sum, over pixels p and maps m, of rbar_m(p)
+// dF_m(p)/dtheta; F_m(p) averages the model over the lattice points of p's
+// 3-sigma stencil (Sec. 3.1, PSF equation), so it equals the sum over lattice
+// points x of fbar(x) dF(x)/dtheta with the transposed stencil
+//   fbar(x, r) = (1/W) sum_p rbar(p) g(|x - x_p|) g(|r - r_p|) [inside the stencil].
+// The blocks tile the lattice (a band of pixels owns the lattice points
+// between its pixels' centres shifted by pad - s/2, the outer bands the
+// margins), so every lattice point's reverse model runs once; a block reads
+// the pixel adjoints of every pixel that reaches it (its frame: the band and
+// a halo of about D pixels), which needs no exchange between workgroups.
+// The block is streamed top to bottom in phases of R lattice rows (any R,
+// independent of s):
 //
 //   ring       the pixel rows of rbar the phase reaches (a ring of
 //              D + 1 + ceil((R - 1) / s) rows, new rows loaded per phase);
@@ -30,6 +33,9 @@
 
 #ifndef GK_LW
 #error "compile with -DGK_LW=<0|1>"
+#endif
+#ifndef GK_KH
+#error "compile with -DGK_KH=<4|6>"
 #endif
 
 namespace gk {
@@ -99,7 +105,9 @@ __device__ inline void chain_rule(const double* th, const GridGeom& g, const dou
         for (int q = 0; q < stride; ++q) out[q] = q < k ? gr[q] : 0.0;
 }
 
-template <int BULGE, int NDISC, int HALO, int LW>
+// KH: horizontal tap pairs per (row phase, column phase), the table's stride
+// (pairs past (D + 1) / 2 are zero), so that the gather's loads issue together
+template <int BULGE, int NDISC, int HALO, int LW, int KH>
 __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     extern __shared__ __align__(16) float smem[];
     const int tid = threadIdx.x, BS = blockDim.x;
@@ -110,21 +118,33 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     const int by = band / a.nbx, bx = band - by * a.nbx;
     const int j0 = by * a.band_h, j1 = min(G.ny, j0 + a.band_h);
     const int c0 = bx * a.band_w, c1 = min(G.nx, c0 + a.band_w);
-    const int NR = j1 - j0, NC = c1 - c0;
-    const int NFR = (NR - 1) * s + 2 * pad + 1;
-    const int vlo = j0 * s + hs, ubase = c0 * s + hs;
-    const int RS = a.rows, NLEV = a.nlev, NCP = NC + 2 * D, RB = a.rb, KP2 = a.KP >> 1;
-    const AdjLayout L = adj_layout(a.band_h, a.band_w, s, pad, D, RS, NLEV, RB, a.KP);
+    // the band owns a block of the lattice: rows [Lr0, Lr1) and columns
+    // [Lc0, Lc1) of the whole padded lattice (lattice row g lies in the
+    // stencils of pixel rows ceil((g - 2 pad) / s) .. floor(g / s)); the
+    // blocks of all bands tile it, the outer bands taking the margins
+    const int NLR = (G.ny - 1) * s + 2 * pad + 1, NLC = (G.nx - 1) * s + 2 * pad + 1;
+    const int own = pad - s / 2;
+    const int Lr0 = by == 0 ? 0 : j0 * s + own, Lr1 = j1 == G.ny ? NLR : j1 * s + own;
+    const int Lc0 = bx == 0 ? 0 : c0 * s + own, Lc1 = c1 == G.nx ? NLC : c1 * s + own;
+    // frame: the pixels whose stencils reach the block (their adjoints are
+    // read, the halo included); frame lattice row r is lattice row jf0 s + r
+    const int jf0 = max(0, ceil_div(Lr0 - 2 * pad, s)), jf1 = min(G.ny, (Lr1 - 1) / s + 1);
+    const int cf0 = max(0, ceil_div(Lc0 - 2 * pad, s)), cf1 = min(G.nx, (Lc1 - 1) / s + 1);
+    const int NR = jf1 - jf0, NC = cf1 - cf0;
+    const int rbeg = Lr0 - jf0 * s, rend = Lr1 - jf0 * s;
+    const int xbeg = Lc0 - cf0 * s, xend = Lc1 - cf0 * s;
+    const int vlo = jf0 * s + hs, ubase = cf0 * s + hs;
+    const int RS = a.rows, NLEV = a.nlev, NCP = NC + 2 * D, RB = a.rb;
+    const AdjLayout L = adj_layout(a.band_h, a.band_w, s, pad, D, RS, NLEV, RB, 2 * KH);
     float* s_tab = smem + L.tab;
     float4* s_ring = (float4*)(smem + L.ring);      // [RB][NC]
     float4* s_S = (float4*)(smem + L.S);            // [RS][NCP][NLEV]
-    const int4* s_ht = (const int4*)(smem + L.ht);  // [s][s][KP2]
+    const int4* s_ht = (const int4*)(smem + L.ht);  // [s][s][KH]
     const int2* s_vt = (const int2*)(smem + L.vt);  // [s][DSTRIDE]
     double* s_red = (double*)(smem + L.red);
     int2* s_span = (int2*)(smem + L.span);
     int* s_aof = (int*)(smem + L.aof);
-    int* s_plo = (int*)(smem + L.plo);
-    int* s_pw = (int*)(smem + L.pw);
+    int* s_prange = (int*)(smem + L.prange);
 
     const double* th = a.theta + (size_t)b * a.stride;
     const TC tc = uniform_tc(make_tc(th, G));
@@ -141,40 +161,41 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
         for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
         int* ht = (int*)(smem + L.ht);
         const int* ght = (const int*)a.ht;
-        for (int i = tid; i < s * s * a.KP * 2; i += BS) ht[i] = ght[i];
+        for (int i = tid; i < s * s * KH * 4; i += BS) ht[i] = ght[i];
         int* vt = (int*)(smem + L.vt);
         const int* gvt = (const int*)a.vt;
         for (int i = tid; i < s * DSTRIDE * 2; i += BS) vt[i] = gvt[i];
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
         for (int i = tid; i < RB * NC; i += BS) s_ring[i] = z;
         for (int i = tid; i < RS * NCP * NLEV; i += BS) s_S[i] = z;
-        for (int i = tid; i < NR; i += BS) s_span[i] = a.span[j0 + i];
+        for (int i = tid; i < NR; i += BS) s_span[i] = a.span[jf0 + i];
         for (int i = tid; i <= pad; i += BS) s_aof[i] = a.aof[i];
     }
     __syncthreads();
-    // needed lattice columns of each phase: the union, over the phase's lattice
-    // rows, of the stencils of the band's valid pixels (elsewhere every pixel
-    // adjoint in reach is zero)
-    const int nph = (NFR + RS - 1) / RS;
+    // needed lattice columns of each phase: the owned columns within the
+    // union, over the phase's lattice rows, of the stencils of the frame's
+    // valid pixels (elsewhere every pixel adjoint in reach is zero)
+    const int nph = (rend - rbeg + RS - 1) / RS;
     for (int k = tid; k < nph; k += BS) {
         int lo = 1 << 30, hi = -(1 << 30);
-        for (int r = k * RS; r < min(NFR, (k + 1) * RS); ++r) {
+        for (int r = rbeg + k * RS; r < min(rend, rbeg + (k + 1) * RS); ++r) {
             const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;
             const int jhi = min(NR - 1, r / s);
             for (int jj = jlo; jj <= jhi; ++jj) {
                 int bb = r - jj * s - pad;
                 bb = bb < 0 ? -bb : bb;
                 const int2 sp = s_span[jj];
-                const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
+                const int cl = max(cf0, sp.x), ch = min(cf1 - 1, sp.y);
                 if (cl <= ch) {
                     const int A = s_aof[bb];
-                    lo = min(lo, cl * s + hs + pad - A);
-                    hi = max(hi, ch * s + hs + pad + A);
+                    lo = min(lo, (cl - cf0) * s + pad - A);
+                    hi = max(hi, (ch - cf0) * s + pad + A);
                 }
             }
         }
-        s_plo[k] = hi >= lo ? lo - ubase : 0;
-        s_pw[k] = hi >= lo ? hi - lo + 1 : 0;
+        lo = max(lo, xbeg);
+        hi = min(hi, xend - 1);
+        s_prange[k] = hi >= lo ? lo | ((hi - lo + 1) << 16) : 0;
     }
     const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
                  (const float4*)(s_tab + TAB_GH + TAB_PHI)};
@@ -189,9 +210,10 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     // Pixel rows of rbar enter a ring of RB rows, slot = row mod RB.  The rows
     // a phase reaches are loaded during the previous phase's gather (the ring
     // is not read then), so a phase needs two barriers.
-    int loaded = -1;                                // last pixel row put in the ring
+    // the first phase reaches pixel rows from rbeg / s - D on
+    int loaded = max(-1, rbeg / s - D - 1);         // last pixel row put in the ring
     auto load_rows = [&](int rA_next) {
-        const int nrow_n = min(RS, NFR - rA_next);
+        const int nrow_n = min(RS, rend - rA_next);
         const int qlo_n = rA_next / s, qhi_n = (rA_next + nrow_n - 1) / s;
         const int base_n = ((qlo_n - D) % RB + RB) % RB;
         const int nnew = qhi_n - loaded;
@@ -200,7 +222,7 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             const int jj = loaded + 1 + k;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (jj < NR) {
-                const size_t pix = (size_t)(j0 + jj) * G.nx + c0 + cc;
+                const size_t pix = (size_t)(jf0 + jj) * G.nx + cf0 + cc;
                 v = make_float4(fb[pix], fb[mstr + pix], fb[2 * mstr + pix], fb[3 * mstr + pix]);
             }
             int slot = base_n + jj - (qlo_n - D);
@@ -209,10 +231,10 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
         }
         loaded = max(loaded, qhi_n);
     };
-    load_rows(0);
+    load_rows(rbeg);
     __syncthreads();
-    for (int rA = 0, ph_i = 0; rA < NFR; rA += RS, ++ph_i) {
-        const int nrow = min(RS, NFR - rA);
+    for (int rA = rbeg, ph_i = 0; rA < rend; rA += RS, ++ph_i) {
+        const int nrow = min(RS, rend - rA);
         // pixel rows [qlo - D, qhi] are in reach of lattice rows [rA, rA + nrow); ring
         // slot of pixel row jj: base + jj - (qlo - D), wrapped, base = (qlo - D) mod RB
         const int qlo = rA / s;
@@ -224,25 +246,34 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             const int qr = (int)(((float)r + 0.5f) * inv_s), ph = r - qr * s;
             const int2* vt = s_vt + ph * DSTRIDE;
             float4* Sp = s_S + ((size_t)rl * NCP + cc + D) * NLEV;
-            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
             const int off0 = base + qr - qlo + D;       // ring position of pixel row qr, unwrapped
-            for (int n = 0; n <= D; ++n) {
-                const int2 e = vt[n];
-                const int d = e.x & 255;
-                const float w = __int_as_float(e.y);
-                int slot = off0 - d;
+            // all DSTRIDE entries (zero past the phase's lags: weight 0, no
+            // store), so that the table and ring loads issue together
+            int2 e[DSTRIDE];
+#pragma unroll
+            for (int n = 0; n < DSTRIDE; ++n) e[n] = vt[n];
+            float4 v[DSTRIDE];
+#pragma unroll
+            for (int n = 0; n < DSTRIDE; ++n) {
+                int slot = off0 - (e[n].x & 255);
                 slot = slot >= RB ? slot - RB : slot;
-                const float4 v = s_ring[slot * NC + cc];
-                acc.x = fmaf(w, v.x, acc.x);
-                acc.y = fmaf(w, v.y, acc.y);
-                acc.z = fmaf(w, v.z, acc.z);
-                acc.w = fmaf(w, v.w, acc.w);
-                if (e.x >> 16) Sp[(e.x >> 8) & 255] = acc;
+                v[n] = s_ring[slot * NC + cc];
+            }
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int n = 0; n < DSTRIDE; ++n) {
+                const float w = __int_as_float(e[n].y);
+                acc.x = fmaf(w, v[n].x, acc.x);
+                acc.y = fmaf(w, v[n].y, acc.y);
+                acc.z = fmaf(w, v[n].z, acc.z);
+                acc.w = fmaf(w, v[n].w, acc.w);
+                if (e[n].x >> 16) Sp[(e[n].x >> 8) & 255] = acc;
             }
         }
         __syncthreads();
         // ---- horizontal gather and reverse point model, flat over the phase's points
-        const int plo = s_plo[ph_i], pw = s_pw[ph_i];
+        const int prange = s_prange[ph_i];
+        const int plo = prange & 0xffff, pw = prange >> 16;
         const int npts = nrow * pw;
         const float inv_pw = 1.0f / (float)max(pw, 1);
         for (int qq = tid; qq < npts; qq += BS) {
@@ -251,12 +282,15 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             const int qr = (int)(((float)(rA + rl) + 0.5f) * inv_s), ph = rA + rl - qr * s;
             const int qx = (int)(((float)x + 0.5f) * inv_s), ix = x - qx * s;
             const float4* Sb = s_S + ((size_t)rl * NCP + qx + D) * NLEV;
-            const int4* h = s_ht + (ph * s + ix) * KP2;
+            const int4* h = s_ht + (ph * s + ix) * KH;
+            int4 e[KH];
+#pragma unroll
+            for (int k2 = 0; k2 < KH; ++k2) e[k2] = h[k2];
             float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
-            for (int k2 = 0; k2 < KP2; ++k2) {
-                const int4 e = h[k2];
-                const float4 v0 = Sb[e.x], v1 = Sb[e.z];
-                const float w0 = __int_as_float(e.y), w1 = __int_as_float(e.w);
+#pragma unroll
+            for (int k2 = 0; k2 < KH; ++k2) {
+                const float4 v0 = Sb[e[k2].x], v1 = Sb[e[k2].z];
+                const float w0 = __int_as_float(e[k2].y), w1 = __int_as_float(e[k2].w);
                 f.x = fmaf(w1, v1.x, fmaf(w0, v0.x, f.x));
                 f.y = fmaf(w1, v1.y, fmaf(w0, v0.y, f.y));
                 f.z = fmaf(w1, v1.z, fmaf(w0, v0.z, f.z));
@@ -278,7 +312,7 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             }
             point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
         }
-        if (rA + RS < NFR) load_rows(rA + RS);      // the next phase's new pixel rows
+        if (rA + RS < rend) load_rows(rA + RS);     // the next phase's new pixel rows
         __syncthreads();
     }
 
@@ -326,13 +360,13 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     }
 }
 
-template <int LW>
+template <int LW, int KH>
 hipError_t launch_adj_lw(int bulge, int nd, int halo, dim3 grid, dim3 block, size_t lds, hipStream_t st,
                          const AdjArgs& a) {
-#define GK_ALAUNCH(BU, ND, HA)                                                        \
-    if (bulge == BU && nd == ND && halo == HA) {                                       \
-        hipLaunchKernelGGL((adj_kernel<BU, ND, HA, LW>), grid, block, lds, st, a);    \
-        return hipGetLastError();                                                      \
+#define GK_ALAUNCH(BU, ND, HA)                                                          \
+    if (bulge == BU && nd == ND && halo == HA) {                                         \
+        hipLaunchKernelGGL((adj_kernel<BU, ND, HA, LW, KH>), grid, block, lds, st, a);  \
+        return hipGetLastError();                                                        \
     }
     GK_ALAUNCH(1, 0, 0) GK_ALAUNCH(1, 0, 1) GK_ALAUNCH(1, 0, 2)
     GK_ALAUNCH(1, 1, 0) GK_ALAUNCH(1, 1, 1) GK_ALAUNCH(1, 1, 2)
@@ -346,6 +380,6 @@ hipError_t launch_adj_lw(int bulge, int nd, int halo, dim3 grid, dim3 block, siz
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_adj_lw<GK_LW>(int, int, int, dim3, dim3, size_t, hipStream_t, const AdjArgs&);
+template hipError_t launch_adj_lw<GK_LW, GK_KH>(int, int, int, dim3, dim3, size_t, hipStream_t, const AdjArgs&);
 
 }  // namespace gk

@@ -232,18 +232,25 @@ static int adj_lds_of(const gk_grid* g, int bh, int bw, int rows) {
 }
 
 // Fraction of the workgroup's thread slots busy in a phase of `rows` lattice
-// rows over a full-width band (the phase's points are spread flat over the
-// threads)
-static double adj_fill(int s, int pad, int bw, int rows) {
-    const int pts = rows * ((bw - 1) * s + 2 * pad + 1);
-    const int passes = (pts + ADJ_BS - 1) / ADJ_BS;
-    return (double)pts / ((double)passes * ADJ_BS);
+// rows, over the column bands of width bw (a phase covers rows x the band's
+// owned lattice columns, spread flat over the threads)
+static double adj_fill(const gk_grid* g, int bw, int rows) {
+    const int nx = g->d.nx, s = g->geo.s, pad = g->geo.pad;
+    const int NLC = (nx - 1) * s + 2 * pad + 1, own = pad - s / 2;
+    double pts = 0.0, slots = 0.0;
+    for (int c0 = 0; c0 < nx; c0 += bw) {
+        const int c1 = std::min(nx, c0 + bw);
+        const int lo = c0 == 0 ? 0 : c0 * s + own, hi = c1 == nx ? NLC : c1 * s + own;
+        const int p = rows * (hi - lo);
+        pts += p;
+        slots += (double)((p + ADJ_BS - 1) / ADJ_BS) * ADJ_BS;
+    }
+    return pts / slots;
 }
 
 // Install an adjoint shape (band_h x band_w pixels, `rows` lattice rows per
 // phase, 0 = chosen here) if it fits the kernel's limits.
 static int set_adj_shape(gk_grid* g, int bh, int bw, int rows) {
-    const int s = g->geo.s, pad = g->geo.pad;
     bh = std::min(bh, g->d.ny);
     bw = std::min(bw, g->d.nx);
     if (bh < 1 || bw < 1) return fail(GK_EINVAL, "adjoint band must be at least 1 x 1");
@@ -255,18 +262,22 @@ static int set_adj_shape(gk_grid* g, int bh, int bw, int rows) {
     if (rows > 0) {
         best = adj_lds_of(g, bh, bw, rows) <= ADJ_LDS_MAX ? rows : 0;
     } else {
-        // best thread fill among the shapes that leave room for three
+        // the most rows, up to 3, that keep >= 85 % of the threads busy, else
+        // the best thread fill, among the shapes that leave room for three
         // workgroups per CU, else among those that fit at all
         for (int cap : {ADJ_LDS_3, ADJ_LDS_MAX}) {
             double fill = -1.0;
+            int r85 = 0, rfill = 0;
             for (int r = 1; r <= RS_CAP; ++r) {
                 if (adj_lds_of(g, bh, bw, r) > cap) break;
-                const double f = adj_fill(s, pad, bw, r);
-                if (f >= fill - 1e-9) {
+                const double f = adj_fill(g, bw, r);
+                if (r <= 3 && f >= 0.85) r85 = r;
+                if (f > fill + 1e-9) {
                     fill = f;
-                    best = r;
+                    rfill = r;
                 }
             }
+            best = r85 ? r85 : rfill;
             if (best) break;
         }
     }
@@ -280,51 +291,47 @@ static int set_adj_shape(gk_grid* g, int bh, int bw, int rows) {
 }
 
 // Default adjoint shape (measured on the 80 x 80, 100 x 100 and 300 x 300
-// benchmark grids): bands as tall as possible (up to 128 rows: each band
-// recomputes a lattice halo of 2 pad rows) and as wide as possible (columns
-// split evenly, at most 80, at least 32 while a wider shape is sought) while
-// a vector still spans at least two bands (more workgroups), with 2 to 4
-// lattice rows per phase: the fewest that reach the best thread fill, which
-// must be >= 90 %, within the LDS that leaves room for three workgroups per
-// CU.  (More rows per phase enlarge the ring and the group sums and measured
-// slower at equal fill.)  Bands grow taller when the grid would need more
-// than MAX_BANDS_ADJ bands.  A grid whose adjoint fits no shape keeps
-// adj_nbands = 0: its forward calls work and its gradient calls return
-// GK_EINVAL.
+// benchmark grids).  A band's block reads a halo of D + 1 pixel columns and
+// rows and restarts its ring, so wide and tall bands are cheapest: widths
+// from even splits of the columns (at most 80) and from 256 / (s r) (a phase
+// of r lattice rows then fills the threads once), widest first, then bands of
+// up to 128 rows (taller if the grid would need more than MAX_BANDS_ADJ
+// bands), while a vector still spans at least two bands (more workgroups).
+// Rows per phase: the most, up to 3, that keep >= 85 % of the threads busy
+// (fewer phases, each with two barriers and a dependent chain of LDS reads)
+// within the LDS that leaves room for three workgroups per CU.  A grid whose
+// adjoint fits no shape keeps adj_nbands = 0: its forward calls work and its
+// gradient calls return GK_EINVAL.
 static int default_adj_shape(gk_grid* g) {
-    const int nx = g->d.nx, ny = g->d.ny, s = g->geo.s, pad = g->geo.pad;
+    const int nx = g->d.nx, ny = g->d.ny, s = g->geo.s;
     const std::string saved = g_err;
     auto split = [](int n, int m) { const int k = (n + m - 1) / m; return (n + k - 1) / k; };
+    std::vector<int> widths;
+    for (int m : {80, 64, 40, 32, 20, 16, 8}) widths.push_back(split(nx, m));
+    for (int r = 1; r <= 4; ++r)
+        if (256 / (s * r) >= 8) widths.push_back(std::min(nx, 256 / (s * r)));
+    std::sort(widths.begin(), widths.end(), [](int x, int y) { return x > y; });
+    widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
     const bool big = nx >= 40 || ny >= 40;          // room for two bands
+    auto try_set = [&](int bh, int bw, int rows) {
+        if (set_adj_shape(g, bh, bw, rows) != GK_OK) return false;
+        g_err = saved;
+        return true;
+    };
     for (int cap : {ADJ_LDS_3, ADJ_LDS_MAX})
         for (int pass = 0; pass < 2; ++pass)        // pass 1: single-band shapes allowed
-            for (int hmax : {128, 64, 256, 512, 1024, 2048, 4096}) {
-                const int bh = split(ny, hmax);
-                int bbw = 0, brows = 0;
-                for (int wmax : {80, 64, 40, 32, 20, 16, 8}) {
-                    if (pass == 0 && wmax < 32) break;
-                    const int bw = split(nx, wmax);
+            for (int bw : widths) {
+                if (bw > 80) continue;
+                for (int hmax : {128, 64, 256, 512, 1024, 2048, 4096}) {
+                    const int bh = split(ny, hmax);
                     const int nb = ((nx + bw - 1) / bw) * ((ny + bh - 1) / bh);
                     if (nb > MAX_BANDS_ADJ || (pass == 0 && big && nb < 2)) continue;
                     int rows = 0;
-                    double fill = -1.0;
-                    for (int r = 2; r <= 4; ++r) {
+                    for (int r = 1; r <= 3; ++r) {
                         if (adj_lds_of(g, bh, bw, r) > cap) break;
-                        const double f = adj_fill(s, pad, bw, r);
-                        if (f > fill + 1e-9) {
-                            fill = f;
-                            rows = r;
-                        }
+                        if (adj_fill(g, bw, r) >= 0.85) rows = r;
                     }
-                    if (rows && fill >= 0.9) {
-                        bbw = bw;
-                        brows = rows;
-                        break;
-                    }
-                }
-                if (bbw && set_adj_shape(g, bh, bbw, brows) == GK_OK) {
-                    g_err = saved;
-                    return GK_OK;
+                    if (rows && try_set(bh, bw, rows)) return GK_OK;
                 }
             }
     // nothing reached the fill target: the best fill of the default heights
@@ -333,12 +340,11 @@ static int default_adj_shape(gk_grid* g) {
             const int bh = split(ny, hmax);
             int bbw = 0, brows = 0;
             double bfill = -1.0;
-            for (int wmax : {80, 64, 40, 32, 20, 16, 8}) {
-                const int bw = split(nx, wmax);
+            for (int bw : widths) {
                 if (((nx + bw - 1) / bw) * ((ny + bh - 1) / bh) > MAX_BANDS_ADJ) continue;
                 for (int r = 1; r <= RS_CAP; ++r) {
                     if (adj_lds_of(g, bh, bw, r) > cap) break;
-                    const double f = adj_fill(s, pad, bw, r);
+                    const double f = adj_fill(g, bw, r);
                     if (f > bfill + 1e-9) {
                         bfill = f;
                         bbw = bw;
@@ -346,10 +352,7 @@ static int default_adj_shape(gk_grid* g) {
                     }
                 }
             }
-            if (bbw && set_adj_shape(g, bh, bbw, brows) == GK_OK) {
-                g_err = saved;
-                return GK_OK;
-            }
+            if (bbw && try_set(bh, bbw, brows)) return GK_OK;
         }
     g_err = saved;
     g->adj_nbands = 0;
@@ -717,7 +720,7 @@ int create_grid(const gk_grid_desc* desc, int max_batch, gk_grid_t* out) {
         }
         nlev = std::max(nlev, (int)groupA[ph].size());
     }
-    const int KP = (D + 2) & ~1;                       // even, >= D + 1
+    const int KP = 2 * adj_kh(D);                      // table stride, even, >= D + 1
     std::vector<int2> aht((size_t)s * s * KP, make_int2(0, 0));
     for (int ph = 0; ph < s; ++ph)
         for (int i = 0; i < s; ++i)
@@ -1062,8 +1065,14 @@ static int run_grad(gk_grid* g, const double* theta, int B, int stride, double* 
         aa.accum = accum;
         if ((size_t)n * aa.nbands >= ((size_t)1 << 31)) return fail(GK_EINVAL, "adjoint grid too large");
         const dim3 grid2((unsigned)(n * aa.nbands)), block2(ADJ_BS);
-        e = g->geo.lw ? launch_adj_lw<1>(g->d.bulge, g->d.n_discs, g->d.halo, grid2, block2, g->adj_lds, st, aa)
-                      : launch_adj_lw<0>(g->d.bulge, g->d.n_discs, g->d.halo, grid2, block2, g->adj_lds, st, aa);
+        const bool kh4 = g->adj_KP == 8;
+        const int bu = g->d.bulge, nd = g->d.n_discs, ha = g->d.halo;
+        if (g->geo.lw)
+            e = kh4 ? launch_adj_lw<1, 4>(bu, nd, ha, grid2, block2, g->adj_lds, st, aa)
+                    : launch_adj_lw<1, 6>(bu, nd, ha, grid2, block2, g->adj_lds, st, aa);
+        else
+            e = kh4 ? launch_adj_lw<0, 4>(bu, nd, ha, grid2, block2, g->adj_lds, st, aa)
+                    : launch_adj_lw<0, 6>(bu, nd, ha, grid2, block2, g->adj_lds, st, aa);
         if (e != hipSuccess) return fail(GK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
     }
     return GK_OK;

@@ -59,6 +59,8 @@ struct Layout {                 // LDS carve-up, identical on host and device
 };
 
 __host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
+// ceil(a / b) for b > 0 and any sign of a
+__host__ __device__ inline int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
 
 // nfin: floats of the per-step exchange buffer of the luminosity-weighted
 // mode (0 otherwise)
@@ -98,7 +100,7 @@ struct AdjArgs {
     const int* aof;         // [pad + 1] stencil half-widths A(|b|)
     const int2* vt;         // [s][DSTRIDE] vertical pass: (d | group << 8 | last-of-group << 16, weight bits)
     const int4* ht;         // [s][s][KP / 2] horizontal taps in pairs: (S offset, weight bits) x 2
-    int KP;                 // horizontal taps per (phase, column phase), even, >= D + 1
+    int KP;                 // table stride: horizontal taps per (phase, column phase), 2 adj_kh(D)
     int nlev;               // groups (S slots) per (lattice row, pixel column)
     int rb;                 // rows of the pixel-adjoint ring buffer, D + 1 + ceil((rows - 1) / s)
     float invW;
@@ -116,30 +118,35 @@ struct AdjArgs {
 };
 
 struct AdjLayout {              // LDS carve-up of the adjoint (4-byte words), host and device
-    int tab, ring, S, vt, ht, red, span, aof, plo, pw, total_bytes;
+    int tab, ring, S, vt, ht, red, span, aof, prange, total_bytes;
 };
 
 __host__ __device__ inline AdjLayout adj_layout(int band_h, int band_w, int s, int pad, int D, int rows, int nlev,
                                                 int rb, int KP) {
+    // a band of band_h x band_w pixels owns at most band_h s + 2 pad + 1
+    // lattice rows, reached by at most band_h + D + 1 pixel rows (and columns)
+    const int nrf = band_h + D + 1, ncf = band_w + D + 1;
     AdjLayout L;
     int off = 0;
     L.tab = off;  off += TAB_ALL;
     off = (off + 3) & ~3;
-    L.ring = off; off += rb * band_w * 4;                          // float4 [rb][band_w]
-    L.S = off;    off += rows * (band_w + 2 * D) * nlev * 4;       // float4 [rows][band_w + 2D][nlev]
+    L.ring = off; off += rb * ncf * 4;                             // float4 [rb][frame columns]
+    L.S = off;    off += rows * (ncf + 2 * D) * nlev * 4;          // float4 [rows][frame columns + 2D][nlev]
     L.ht = off;   off += s * s * KP * 2;                           // int4 [s][s][KP / 2]
     L.vt = off;   off += s * DSTRIDE * 2;                          // int2 [s][DSTRIDE]
     off = (off + 1) & ~1;
-    L.red = off;  off += RED_SLOTS * NCONST * 2;                   // doubles
-    const int nfrm = nfr_max(band_h, s, pad);
-    L.span = off; off += 2 * band_h;
+    L.red = off;  off += (ADJ_BS / 64) * NCONST * 2;               // doubles, one row per wave
+    L.span = off; off += 2 * nrf;
     L.aof = off;  off += pad + 1;
-    const int nch = (nfrm + rows - 1) / rows + 1;
-    L.plo = off;  off += nch;
-    L.pw = off;   off += nch;
+    const int nch = (band_h * s + 2 * pad + 1 + rows - 1) / rows + 1;
+    L.prange = off; off += nch;                                    // per phase: first column | width << 16
     L.total_bytes = 4 * off;
     return L;
 }
+
+// tap pairs of the adjoint's horizontal table for lag depth D (a compile-time
+// stride of the adjoint kernel; the D + 1 taps fill the first ceil((D + 1) / 2))
+__host__ __device__ constexpr int adj_kh(int D) { return D <= 6 ? 4 : 6; }
 
 constexpr int MULTI_BS = 256;   // threads per workgroup of the many-grid launch
 
@@ -151,7 +158,7 @@ hipError_t launch_fwd(int bulge, int ndisc, int halo, dim3 grid, dim3 block, siz
 template <int LW>
 hipError_t launch_multi(dim3 grid, dim3 block, size_t lds, hipStream_t st, const FwdArgs* grids, const int4* items,
                         const double* theta, int stride, double* logL);
-template <int LW>
+template <int LW, int KH>
 hipError_t launch_adj_lw(int bulge, int ndisc, int halo, dim3 grid, dim3 block, size_t lds, hipStream_t st,
                          const AdjArgs& a);
 
