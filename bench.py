@@ -82,6 +82,12 @@ def flops_per_pixel(spec, n_maps: int = 4) -> int:
     return n_maps * (s * (1 + 3 * pad) + 2 * (2 * pad + 1) + 5) + 1 + lw
 
 
+def adjoint_tap_pairs(spec) -> int:
+    """The adjoint kernel variant: horizontal tap pairs per table row (4 for a
+    lag depth D = floor(2 pad / s) <= 6, else 6)."""
+    return 4 if 2 * stencil_pad(spec) // spec.supersample <= 6 else 6
+
+
 def flops_adjoint_per_point(spec) -> int:
     """Adjoint kernel, per needed lattice point: the point model recomputed
     with the derivatives of its special functions, its reverse sweep into the
@@ -731,7 +737,7 @@ def run_single(args, name, *, steps, warmup, grad_steps, hmc_steps, plain, with_
         roof_adj = {"bound": "alu", "achieved": round(a_ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(a_ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
                     "frac_of_nonpacked_fp32": round(a_ach / PEAK_FP32_NONPACKED, 4),
-                    "kernel": f"gk::adj_kernel<{spec.bulge},{spec.n_discs},{spec.halo},{lw}>",
+                    "kernel": f"gk::adj_kernel<{spec.bulge},{spec.n_discs},{spec.halo},{lw},{adjoint_tap_pairs(spec)}>",
                     "kernel_ms": round(ms_adj, 4),
                     "kernel_ms_from": "gradient step minus forward step (HIP events)",
                     "flop_per_vector": n_need * fa,
