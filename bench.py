@@ -125,14 +125,18 @@ def needed_points(spec, mask) -> int:
     return int(need.sum())
 
 
+# the sources the forward kernel is compiled from (the traffic records are
+# counters of that kernel, valid only for the code they were taken on)
+FWD_SOURCES = ("fwd_inst.hip", "gk_fwd.h", "gk_kern.h", "gk_device.h", "gk_tables.h")
+
+
 def source_hash() -> str:
-    """Hash of the HIP sources (traffic counters are only valid for the kernels they were taken on)."""
+    """Hash of the forward kernel's HIP sources."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2205_06819_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in FWD_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -195,6 +195,7 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
         }
         lo = max(lo, xbeg);
         hi = min(hi, xend - 1);
+        // frame columns < 2^15 (band_w <= 128, D <= 10, s <= 15): both fields fit
         s_prange[k] = hi >= lo ? lo | ((hi - lo + 1) << 16) : 0;
     }
     const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
