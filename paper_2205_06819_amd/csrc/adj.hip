@@ -131,8 +131,11 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     const int jf0 = max(0, ceil_div(Lr0 - 2 * pad, s)), jf1 = min(G.ny, (Lr1 - 1) / s + 1);
     const int cf0 = max(0, ceil_div(Lc0 - 2 * pad, s)), cf1 = min(G.nx, (Lc1 - 1) / s + 1);
     const int NR = jf1 - jf0, NC = cf1 - cf0;
-    const int rbeg = Lr0 - jf0 * s, rend = Lr1 - jf0 * s;
-    const int xbeg = Lc0 - cf0 * s, xend = Lc1 - cf0 * s;
+    // block rows and columns before the frame's first lattice row / column
+    // (possible when pad < s / 2) are reached by no pixel: they start at 0,
+    // so every index below is non-negative
+    const int rbeg = max(0, Lr0 - jf0 * s), rend = Lr1 - jf0 * s;
+    const int xbeg = max(0, Lc0 - cf0 * s), xend = Lc1 - cf0 * s;
     const int vlo = jf0 * s + hs, ubase = cf0 * s + hs;
     const int RS = a.rows, NLEV = a.nlev, NCP = NC + 2 * D, RB = a.rb;
     const AdjLayout L = adj_layout(a.band_h, a.band_w, s, pad, D, RS, NLEV, RB, 2 * KH);

@@ -102,8 +102,12 @@ def run_blocks(ny, nx, s, sigma_px, bh, bw, R, mask, rng, end_slip=0):
             assert jf1 == ny or jf1 * s > Lr1 - 1
             assert cf0 == 0 or (cf0 - 1) * s + 2 * pad < Lc0
             assert cf1 == nx or cf1 * s > Lc1 - 1
-            rbeg, rend = Lr0 - jf0 * s, Lr1 - jf0 * s
-            xbeg, xend = Lc0 - cf0 * s, Lc1 - cf0 * s
+            # rows / columns of the block before the frame's first lattice row /
+            # column are reached by no pixel (pad < s / 2); the kernel divides
+            # with C semantics, so every index it divides must be non-negative
+            rbeg, rend = max(0, Lr0 - jf0 * s), Lr1 - jf0 * s
+            xbeg, xend = max(0, Lc0 - cf0 * s), Lc1 - cf0 * s
+            assert rbeg >= 0 and xbeg >= 0
             NCP = NC + 2 * D
             nph = ceil_div(rend - rbeg, R)
             assert nph <= nph_max
@@ -140,6 +144,7 @@ def run_blocks(ny, nx, s, sigma_px, bh, bw, R, mask, rng, end_slip=0):
                 base = (qlo - D) % RB
                 for rl in range(nrow):
                     r = rA + rl
+                    assert r >= 0
                     qr, ph = r // s, r % s
                     acc = np.zeros(NC)
                     for (d, grp, last, w) in vt[ph]:
@@ -154,6 +159,7 @@ def run_blocks(ny, nx, s, sigma_px, bh, bw, R, mask, rng, end_slip=0):
                     r = rA + rl
                     flat = S[rl].reshape(-1)
                     for x in range(lo, lo + pw):
+                        assert x >= 0
                         qx, ix = x // s, x % s
                         f = 0.0
                         for (off, w) in ht[(r % s) * s + ix]:
@@ -177,6 +183,8 @@ CASES = [  # (ny, nx, s, PSF sigma in pixels, band_h, band_w, lattice rows per p
     (12, 11, 5, 1.6986, 3, 3, 3),
     (7, 9, 1, 1.5, 2, 3, 4),
     (6, 6, 3, 0.0, 2, 2, 2),
+    (20, 21, 3, 0.0, 3, 3, 2),
+    (7, 6, 7, 0.05, 2, 3, 1),
     (5, 7, 7, 0.3, 2, 3, 3),
     (8, 9, 5, 1.70, 8, 2, 16),
     (11, 10, 3, 1.0617, 4, 10, 3),
