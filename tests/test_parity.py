@@ -129,7 +129,7 @@ def test_maps_and_loglike_match_oracle(gk, name):
     grid.close()
 
 
-@pytest.mark.parametrize("name", ["ragged_s3_2d_hq", "lw_2d_nfw"])
+@pytest.mark.parametrize("name", ["ragged_s3_2d_hq", "lw_2d_nfw", "no_psf", "jaffe_1d_hq_s1", "bulge_only_s5"])
 def test_band_shapes_do_not_change_results(gk, name):
     spec, data, err, thetas = make_case(name)
     say(f"[parity] band shapes on {name}")
