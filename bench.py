@@ -186,6 +186,31 @@ def host_info() -> dict:
             "worker_cap": 16, "worker_cap_reason": "host CPU share of one GPU on the benchmark machines"}
 
 
+def device_info() -> dict:
+    """The GPU the numbers were taken on: name, compute units, memory and the
+    highest shader clock level the driver lists (the peaks above assume 256
+    CUs at 2.4 GHz)."""
+    info = {}
+    try:
+        import torch
+        p = torch.cuda.get_device_properties(0)
+        info = {"name": p.name, "arch": getattr(p, "gcnArchName", ""), "compute_units": p.multi_processor_count,
+                "memory_gib": round(p.total_memory / 2 ** 30, 1)}
+    except Exception as exc:  # report, do not hide
+        info = {"error": str(exc)}
+    sclk = None
+    try:
+        import glob
+        for f in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+            levels = [int(l.split(":")[1].strip().lower().rstrip("mhz").strip()) for l in open(f) if ":" in l]
+            if levels:
+                sclk = max(levels) if sclk is None else max(sclk, max(levels))
+    except (OSError, ValueError):
+        pass
+    info["max_sclk_mhz"] = sclk
+    return info
+
+
 def cpu_baseline(spec, data, err, thetas, budget_s: float = 20.0, min_n: int = 0):
     """The oracle's log-likelihood on a bounded sample of the batch: about
     budget_s of CPU work per worker, at least min_n vectors."""
@@ -857,6 +882,7 @@ def main():
     }
     if secondary:
         line["secondary"] = secondary
+    line["device"] = device_info()
     print(json.dumps(line), flush=True)
 
 
