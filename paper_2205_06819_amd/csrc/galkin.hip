@@ -181,14 +181,20 @@ static int default_rules(gk_grid* g) {
     g->rules.clear();
     // the grid split into near-equal bands of at most 40 pixels each way; a
     // wide PSF on a coarse lattice (lag D >= 9 pixel rows, e.g. no
-    // supersampling) spends D of every band_h + D steps filling the lag, so
-    // there bands grow to 16 D rows and 64 columns (measured 1.4x faster on a
-    // 160 x 160 grid with D = 10)
+    // supersampling, or 5x5 supersampling of a 4 px FWHM) spends D of every
+    // band_h + D steps filling the lag and recomputes a 2 pad halo, so there
+    // bands grow to 32 D rows and 64 columns (measured 1.4x faster on a
+    // 160 x 160 grid with D = 10; on the 300 x 300, s = 5 grid 300 x 64 bands
+    // take 154.2 ms per 8192 vectors against 162.7 for 150 x 60); a grid with
+    // at least four full 64-pixel bands uses exactly 64 columns, so that the
+    // stencil phase's 4 x 64 threads are whole waves (the narrower last band
+    // costs less; with fewer bands an even split measured faster)
     // (the luminosity-weighted mode, whose phases end in a moment exchange,
     // prefers 80-row bands: measured 6 % faster on the realistic cube)
-    const int hmax = g->D >= 9 ? 16 * g->D : (g->geo.lw ? 80 : 40), wmax = g->D >= 9 ? 64 : 40;
+    const int hmax = g->D >= 9 ? 32 * g->D : (g->geo.lw ? 80 : 40), wmax = g->D >= 9 ? 64 : 40;
     int bh = (ny + (ny + hmax - 1) / hmax - 1) / ((ny + hmax - 1) / hmax);
     int bw = (nx + (nx + wmax - 1) / wmax - 1) / ((nx + wmax - 1) / wmax);
+    if (g->D >= 9 && nx >= 4 * 64) bw = 64;
     fit_shape(g, bh, bw, 0);
     // on the 3x3 lattice two pixel rows (six lattice rows) per model phase: the
     // smaller row buffer leaves LDS for a fifth workgroup per CU (measured 6 %

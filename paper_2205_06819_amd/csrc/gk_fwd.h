@@ -7,36 +7,6 @@
 
 namespace gk {
 
-__device__ inline int block_exclusive_scan(int* a, int n, int* scratch /*RED_SLOTS ints*/) {
-    const int tid = threadIdx.x, BS = blockDim.x;
-    const int per = (n + BS - 1) / BS;
-    const int lo = min(n, tid * per), hi = min(n, lo + per);
-    int sum = 0;
-    for (int i = lo; i < hi; ++i) sum += a[i];
-    const int lane = tid & 63, wave = tid >> 6;
-    int x = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) scratch[wave] = x;
-    __syncthreads();
-    int wbase = 0;
-    const int nw = (BS + 63) >> 6;
-    for (int w = 0; w < wave; ++w) wbase += scratch[w];
-    int total = 0;
-    for (int w = 0; w < nw; ++w) total += scratch[w];
-    int run = wbase + x - sum;                      // exclusive prefix of this thread
-    for (int i = lo; i < hi; ++i) {
-        const int v = a[i];
-        a[i] = run;
-        run += v;
-    }
-    __syncthreads();
-    return total;
-}
-
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -107,8 +77,7 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     float* s_tab = smem + L.tab;
     float* s_rows = smem + L.rows;
     double* s_red = (double*)(smem + L.red);
-    int* s_lo = (int*)(smem + L.rows_lo);
-    int* s_start = (int*)(smem + L.rows_start);
+    int* s_prange = (int*)(smem + L.prange);
     float* s_fin = smem + L.fin;                    // [2][gsub][4][band_w] (luminosity-weighted mode)
     const int XW = a.xw;
     const int D = a.D;
@@ -142,40 +111,30 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     for (int i = tid; i < NR; i += BS) s_span[i] = MODE != MODE_MAPS ? a.span[j0 + i] : make_int2(c0, c1 - 1);
     for (int i = tid; i <= pad; i += BS) s_aof[i] = a.aof[i];
     __syncthreads();
-    for (int r = tid; r < NFR; r += BS) {
-        const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;   // ceil((r - 2 pad) / s)
-        const int jhi = min(NR - 1, r / s);
-        int lo = 1 << 30, hi = -(1 << 30);
-        for (int jj = jlo; jj <= jhi; ++jj) {
-            int bb = r - jj * s - pad;
-            bb = bb < 0 ? -bb : bb;
-            const int2 sp = s_span[jj];
-            const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
-            if (cl <= ch) {
-                const int A = s_aof[bb];
-                lo = min(lo, cl * s + hs + pad - A);
-                hi = max(hi, ch * s + hs + pad + A);
-            }
-        }
-        s_lo[r] = hi >= lo ? lo - ubase : (1 << 30);  // local needed columns of lattice row r
-        s_start[r] = hi >= lo ? hi - ubase : -(1 << 30);
-    }
-    __syncthreads();
-    // one column range per model phase: the union of its lattice rows' ranges
-    // (about 3 % more points than row by row, and no per-point row search)
+    // one column range per model phase: the union, over its lattice rows, of
+    // the stencils of the band's valid pixels (about 3 % more points than row
+    // by row, and no per-point row search); local columns < 2^15 (band_w <=
+    // 128, s <= 15, pad <= 25), so first column and width pack in one int
     const int RSs = a.gsub * s;
     const int nph = (NFR + RSs - 1) / RSs;
-    int* s_plo = (int*)(smem + L.stage);                // reuses the staging area
-    int* s_pw = s_plo + nph;
-    __syncthreads();
     for (int k = tid; k < nph; k += BS) {
         int lo = 1 << 30, hi = -(1 << 30);
         for (int r = k * RSs; r < min(NFR, (k + 1) * RSs); ++r) {
-            lo = min(lo, s_lo[r]);
-            hi = max(hi, s_start[r]);
+            const int jlo = r >= 2 * pad ? (r - 2 * pad + s - 1) / s : 0;   // ceil((r - 2 pad) / s)
+            const int jhi = min(NR - 1, r / s);
+            for (int jj = jlo; jj <= jhi; ++jj) {
+                int bb = r - jj * s - pad;
+                bb = bb < 0 ? -bb : bb;
+                const int2 sp = s_span[jj];
+                const int cl = max(c0, sp.x), ch = min(c1 - 1, sp.y);
+                if (cl <= ch) {
+                    const int A = s_aof[bb];
+                    lo = min(lo, (cl - c0) * s + pad - A);
+                    hi = max(hi, (ch - c0) * s + pad + A);
+                }
+            }
         }
-        s_plo[k] = hi >= lo ? lo : 0;
-        s_pw[k] = hi >= lo ? hi - lo + 1 : 0;
+        s_prange[k] = hi >= lo ? lo | ((hi - lo + 1) << 16) : 0;
     }
     __syncthreads();
 
@@ -200,7 +159,8 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
         const int rA = q0 * s;
         const int nrow = max(0, min(RS, NFR - rA));
         const int ph = q0 / a.gsub;
-        const int plo = uni(s_plo[ph]), pw = uni(s_pw[ph]);
+        const int prange = uni(s_prange[ph]);
+        const int plo = prange & 0xffff, pw = prange >> 16;
         const int npts = nrow * pw;
         const float inv_pw = 1.0f / (float)max(pw, 1);
         // ---- data of the pixel rows completed in this phase (prefetched)

@@ -55,7 +55,7 @@ constexpr int RS_CAP = 16;      // lattice rows per model phase
 constexpr int GSUB_CAP = 4;     // pixel-row steps per model phase
 
 struct Layout {                 // LDS carve-up, identical on host and device
-    int tab, rows, red, rows_lo, rows_start, stage, fin, total_bytes;
+    int tab, rows, red, stage, prange, fin, total_bytes;
 };
 
 __host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
@@ -70,10 +70,8 @@ __host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int ba
     L.rows = off;       off += rows * 4 * xw;
     off = (off + 3) & ~3;
     L.red = off;        off += 2 * RED_SLOTS;      // doubles
-    L.rows_lo = off;    off += nfrm;
-    L.rows_start = off; off += nfrm + 1 + RS_CAP;  // padded: phase lookups read ahead
-    off = (off + 1) & ~1;
     L.stage = off;      off += 2 * band_h + 32;    // row spans and stencil half-widths
+    L.prange = off;     off += (nfrm + rows - 1) / rows + 1;   // per phase: first column | width << 16
     L.fin = off;        off += nfin;
     // the tables last, at a launch-dependent offset: a table lookup is then one
     // base add and four reads with immediate offsets
