@@ -252,12 +252,16 @@ int set_launch_shape(gk_grid_t grid, int batch_min, int band_h, int band_w, int 
  * which time this shape alongside their own candidates. */
 int get_launch_shape(gk_grid_t grid, int B, int* band_h, int* band_w, int* steps);
 
-/* Launch shape of the gradient's second pass (the adjoint kernel): bands of
- * band_h x band_w pixels per workgroup (band_w <= 128, at most 1024 bands)
- * and `rows` lattice rows per phase (1..16; 0 = chosen from the band width).
- * GK_EINVAL if the shape does not fit the kernel's limits (80 KiB of LDS).
- * Not a hot-path call: it may allocate the per-band gradient partials and
- * then synchronises the device.  For autotuners. */
+/* Launch shape of the gradient's second pass (the adjoint kernel): one
+ * workgroup per vector and band of band_h x band_w pixels (band_w <= 128, at
+ * most 1024 bands), which evaluates the block of the supersampled lattice
+ * that its band owns (the lattice points between its pixels' centres, the
+ * outer bands also the margins) and reads the pixel adjoints of every pixel
+ * reaching that block; `rows` lattice rows per phase (1..16; 0 = chosen
+ * from the band width).  The shape changes only the FP32 summation order of
+ * the gradient.  GK_EINVAL if the shape does not fit the kernel's limits
+ * (80 KiB of LDS).  Not a hot-path call: it may allocate the per-band
+ * gradient partials and then synchronises the device.  For autotuners. */
 int set_adjoint_shape(gk_grid_t grid, int band_h, int band_w, int rows);
 
 /* The adjoint's current launch shape (band_h, band_w, rows), written to host
