@@ -417,8 +417,10 @@ template <int MODE>
 static hipError_t enqueue_fwd(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, int B, hipStream_t st) {
     if ((size_t)B * c.nbands * c.BS >= ((size_t)1 << 31)) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)(B * c.nbands)), block((unsigned)c.BS);
-    return a.geo.lw ? launch_fwd<MODE, 1>(g->d.bulge, g->d.n_discs, g->d.halo, grid, block, c.lds, st, a)
-                    : launch_fwd<MODE, 0>(g->d.bulge, g->d.n_discs, g->d.halo, grid, block, c.lds, st, a);
+    // a grid whose only valid map is B runs the light-only model
+    const int bonly = MODE != MODE_MAPS && !a.geo.lw && a.map_mask == 1;
+    return a.geo.lw ? launch_fwd<MODE, 1>(g->d.bulge, g->d.n_discs, g->d.halo, 0, grid, block, c.lds, st, a)
+                    : launch_fwd<MODE, 0>(g->d.bulge, g->d.n_discs, g->d.halo, bonly, grid, block, c.lds, st, a);
 }
 
 static int check_call(const gk_grid* g, const double* theta, int B, int stride, const void* out) {

@@ -328,7 +328,7 @@ __device__ __forceinline__ void point_model(const TC& c, const Tabs& T, float du
     float vc2 = 0.0f, Bt = 0.0f, BS = 0.0f, kB = 0.0f, sB = 0.0f, mass = 0.0f;
     float scale = 1.0f;
     if (BULGE) {
-        const float R = fsqrt(x2 + y2);
+        const float R = fsqrt(fmaf(xp, xp, y2));
         const float sb = fmaxf(R * c.invRb, S_MIN);
         float g, h;
         eval_gh<BULGE == 2>(T.gh, sb, g, h);
@@ -353,7 +353,7 @@ __device__ __forceinline__ void point_model(const TC& c, const Tabs& T, float du
     for (int j = 0; j < NDISC; ++j) {
         ex[j] = fexp2(fmaf(r, c.nl2Rd[j], -eref));
         const float Bd = c.Ad[j] * ex[j];
-        Bt += Bd;
+        Bt = fmaf(c.Ad[j], ex[j], Bt);              // as in point_model_b
         kB = fmaf(Bd, c.kf[j], kB);
         sB = fmaf(Bd, c.sf[j], sB);
         mass = fmaf(Bd, c.MLd[j], mass);
@@ -371,6 +371,49 @@ __device__ __forceinline__ void point_model(const TC& c, const Tabs& T, float du
     oV = cphi * vint * kB * ib;
     oS = fsqrt(fmaf(vc2, sB, BS) * ib);
     oLM = Bt * frcp(mass);
+}
+
+// The surface brightness alone (B of point_model, bit for bit: the same
+// operations, every multiply-add written as one fmaf so that contraction
+// cannot differ), for grids whose only valid map is B: the halo and the
+// kinematics do not enter it.
+template <bool JF>
+__device__ __forceinline__ float eval_g(const float4* __restrict__ T, float s) {
+    if (s < 4096.0f) {
+        float u;
+        const int k = piece(s, GK_S_ELO, u);
+        return horner8(T[4 * k], T[4 * k + 1], u);
+    }
+    const float w = frcp(s), w3 = w * w * w;
+    return w3 * tail_g<JF>(w);
+}
+
+template <int BULGE, int NDISC>
+__device__ __forceinline__ float point_model_b(const TC& c, const Tabs& T, float du, float dv) {
+    const float xp = fmaf(du, c.ca, dv * c.sa);
+    const float yp = fmaf(dv, c.ca, -du * c.sa);
+    const float y2 = yp * yp;
+    float Bt = 0.0f, scale = 1.0f, r = 0.0f;
+    if (NDISC > 0) {
+        const float x2 = xp * xp;
+        const float r2 = fmaf(y2, c.sec2i, x2);
+        const float rinv = r2 > 0.0f ? frsq(r2) : 0.0f;
+        r = r2 * rinv;
+    }
+    if (BULGE) {
+        const float R = fsqrt(fmaf(xp, xp, y2));
+        const float sb = fmaxf(R * c.invRb, S_MIN);
+        Bt = c.Ab * eval_g<BULGE == 2>(T.gh, sb);
+    }
+    float eref = 0.0f;
+    if (!BULGE && NDISC > 0) {
+        eref = r * c.nl2Rd[0];
+        if (NDISC > 1) eref = fmaxf(eref, r * c.nl2Rd[1]);
+        scale = fexp2(eref);
+    }
+#pragma unroll
+    for (int j = 0; j < NDISC; ++j) Bt = fmaf(c.Ad[j], fexp2(fmaf(r, c.nl2Rd[j], -eref)), Bt);
+    return Bt * scale;
 }
 
 // ---------------------------------------------------------------------------

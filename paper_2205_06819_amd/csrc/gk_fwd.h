@@ -58,9 +58,14 @@ __device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rs
 // when the caller already staged the special-function tables in LDS.  LW = 1:
 // the PSF averages luminosity-weighted moments (a compile-time switch, so the
 // map-averaging instantiations do not carry its registers).
-template <int BULGE, int NDISC, int HALO, int MODE, int LW>
+// BO = 1: the grid's only valid map is B (a photometric grid; never with
+// MODE_MAPS or LW): the model phase evaluates the surface brightness alone
+// (point_model_b, equal bit for bit to point_model's B) and leaves the other
+// three rows of the buffer at zero, which the stencil skips anyway.
+template <int BULGE, int NDISC, int HALO, int MODE, int LW, int BO = 0>
 __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const int band, float* smem,
                                          const bool load_tables) {
+    static_assert(!BO || (MODE != MODE_MAPS && !LW), "the light-only body computes B alone");
     const int tid = threadIdx.x, BS = blockDim.x;
     const GridGeom& G = a.geo;
     const int s = G.s, pad = G.pad, hs = G.hs;
@@ -186,9 +191,13 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
             const int v = vlo + r;
             const float du = (float)(u - tc.Ui) - tc.Uf;
             const float dv = (float)(v - tc.Vi) - tc.Vf;
+            float* row = s_rows + lr * 4 * XW + x;
+            if (BO) {
+                row[0] = point_model_b<BULGE, NDISC>(tc, T, du, dv);
+                continue;
+            }
             float fB, fV, fS, fL;
             point_model<BULGE, NDISC, HALO>(tc, T, du, dv, fB, fV, fS, fL);
-            float* row = s_rows + lr * 4 * XW + x;
             if (LW) {         // light, first and second velocity moments, mass
                 row[0] = fB;
                 row[XW] = fB * fV;
@@ -348,10 +357,10 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     }
 }
 
-template <int BULGE, int NDISC, int HALO, int MODE, int LW>
+template <int BULGE, int NDISC, int HALO, int MODE, int LW, int BO = 0>
 __global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
     extern __shared__ __align__(16) float smem[];
-    fwd_band<BULGE, NDISC, HALO, MODE, LW>(a, blockIdx.x / a.nbands, blockIdx.x % a.nbands, smem, true);
+    fwd_band<BULGE, NDISC, HALO, MODE, LW, BO>(a, blockIdx.x / a.nbands, blockIdx.x % a.nbands, smem, true);
 }
 
 }  // namespace gk

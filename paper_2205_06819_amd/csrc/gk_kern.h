@@ -150,8 +150,10 @@ constexpr int MULTI_BS = 256;   // threads per workgroup of the many-grid launch
 
 // launch entry points (each defined in one kernel translation unit); they
 // enqueue one launch on the stream and return hipGetLastError()
+// bonly: the light-only body (a grid whose only valid map is B; log-likelihood
+// modes of map averaging only, else hipErrorInvalidValue)
 template <int MODE, int LW>
-hipError_t launch_fwd(int bulge, int ndisc, int halo, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+hipError_t launch_fwd(int bulge, int ndisc, int halo, int bonly, dim3 grid, dim3 block, size_t lds, hipStream_t st,
                       const FwdArgs& a);
 template <int LW>
 hipError_t launch_multi(dim3 grid, dim3 block, size_t lds, hipStream_t st, const FwdArgs* grids, const int4* items,

@@ -123,6 +123,33 @@ def test_joint_of_split_maps_equals_one_grid(gk):
         g.close()
 
 
+@pytest.mark.parametrize("comp", [(1, 2, 2), (2, 1, 0), (0, 2, 1)])
+def test_light_only_grid_equals_full_model(gk, comp):
+    """A grid whose only valid map is B runs the light-only model (bulge and
+    discs, no halo or kinematics); its log-likelihoods and dlogL/dB equal,
+    bit for bit, those of the full model that the many-grid launch runs."""
+    spec = W.GridSpec(41, 37, 0.2, 1, 1.6, *comp)
+    rng = np.random.default_rng(zlib.crc32(repr(comp).encode()))
+    truth = W.draw_thetas(spec, 1, rng)[0]
+    data, err = M.synthetic_data(spec, truth, W.elliptical_mask(spec.nx, spec.ny, 18.0, 15.0), rng)
+    err[1:] = 0.0                                       # B only
+    th = torch.tensor(np.vstack([truth[None], W.draw_thetas(spec, 15, rng)]), device="cuda")
+    g = gk.Grid(spec, max_batch=16)
+    g.set_data(data, err)
+    say(f"[light-only] components {comp}, {spec.nx}x{spec.ny}, s = 1")
+    single = g.loglike(th).cpu().numpy()
+    multi = gk.loglike_multi([g.handle], th, np.array([0, 16], dtype=np.int32)).cpu().numpy()
+    np.testing.assert_array_equal(single, multi)
+    lg, grad = g.loglike_grad(th)
+    np.testing.assert_array_equal(lg.cpu().numpy(), single)
+    for k in range(2):
+        ref = M.grad_complex_step(spec, data, err, th[k].cpu().numpy())
+        check_grad(grad[k].cpu().numpy(), ref, f"light-only {comp} row {k}")
+    lo = M.loglike(spec, data, err, truth)
+    assert abs(single[0] - lo) <= LOGL_ATOL, (single[0], lo)
+    g.close()
+
+
 def test_joint_argument_errors(gk):
     a = gk.Grid(KIN, max_batch=4)
     other = gk.Grid(W.GridSpec(19, 17, 0.2, 3, 1.0, 1, 1, W.HALO_NFW), max_batch=4)
