@@ -68,6 +68,25 @@ def flops_per_point(spec) -> int:
     return f
 
 
+def flops_per_point_light(spec) -> int:
+    """The light-only body (grids whose only valid map is B): the surface
+    brightness alone, no halo or kinematics."""
+    f = 7 + (5 if spec.n_discs else 0)       # rotate; deprojected radius for the discs
+    if spec.bulge:
+        f += 19                              # R, s, g polynomial, B
+    f += 5 * spec.n_discs                    # exp and the weighted sum
+    if not spec.bulge and spec.n_discs:
+        f += 3                               # reference exponential
+    return f + 1
+
+
+def light_only(data, err) -> bool:
+    """True when B is the only map with a valid pixel (the library then runs
+    its light-only forward body in the log-likelihood passes)."""
+    valid = np.isfinite(data) & np.isfinite(err) & (err > 0)
+    return bool(valid[0].any()) and not bool(valid[1:].any())
+
+
 def stencil_pad(spec) -> int:
     return int(math.floor(3.0 * spec.psf_sigma_px * spec.supersample))
 
@@ -535,16 +554,20 @@ def bench_multires(args):
         gbuf = torch.empty(B, th.shape[1], dtype=torch.float64, device=dev)
         msg = timed(lambda: gk.loglike_joint(hs, th, out, grad=gbuf), max(1, args.steps // 2))
         grad_info = {"grad_ms_per_step": round(msg, 4), "grad_evals_per_s": round(B / (msg * 1e-3), 1)}
-    flops = []
-    for w, maps_kept in zip((wp, wk), carried):
+    flops, light = [], []
+    for w, maps_kept, (d_w, e_w) in zip((wp, wk), carried, datas):
         n_need = needed_points(w.spec, w.mask())
-        flops.append(n_need * flops_per_point(w.spec) + int(w.mask().sum()) * flops_per_pixel(w.spec, len(maps_kept)))
+        lo = light_only(d_w, e_w) and not w.spec.psf_mode
+        light.append(int(lo))
+        fp = flops_per_point_light(w.spec) if lo else flops_per_point(w.spec)
+        flops.append(n_need * fp + int(w.mask().sum()) * flops_per_pixel(w.spec, len(maps_kept)))
     dom = int(np.argmax(per))
     wd = (wp, wk)[dom]
     achieved = flops[dom] * B / (per[dom] * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "kernel": f"gk::fwd_kernel<{wd.spec.bulge},{wd.spec.n_discs},{wd.spec.halo},0,{wd.spec.psf_mode}> ({wd.name})",
+            "kernel": f"gk::fwd_kernel<{wd.spec.bulge},{wd.spec.n_discs},{0 if light[dom] else wd.spec.halo},0,"
+                      f"{wd.spec.psf_mode},{light[dom]}> ({wd.name})",
             "flop_per_vector": flops[dom], "per_grid_ms": [round(x, 4) for x in per]}
     cpu = None
     if not args.no_cpu:
@@ -751,7 +774,7 @@ def run_single(args, name, *, steps, warmup, grad_steps, hmc_steps, plain, with_
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
             "frac_of_nonpacked_fp32": round(achieved / PEAK_FP32_NONPACKED, 4),
-            "kernel": f"gk::fwd_kernel<{spec.bulge},{spec.n_discs},{spec.halo},0,{lw}>",
+            "kernel": f"gk::fwd_kernel<{spec.bulge},{spec.n_discs},{spec.halo},0,{lw},0>",
             "kernel_ms": round(ms_step, 4),
             "flop_per_vector": flop_theta,
             "per_unit": {"lattice_points": n_need, "flop_per_point": flops_per_point(spec),
