@@ -107,8 +107,11 @@ __device__ inline void chain_rule(const double* th, const GridGeom& g, const dou
 
 // KH: horizontal tap pairs per (row phase, column phase), the table's stride
 // (pairs past (D + 1) / 2 are zero), so that the gather's loads issue together
-template <int BULGE, int NDISC, int HALO, int LW, int KH>
+// BO = 1: the grid's only valid map is B (never with LW): the light-only
+// reverse model (point_model_adj_b), the other maps' adjoints being zero.
+template <int BULGE, int NDISC, int HALO, int LW, int KH, int BO = 0>
 __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
+    static_assert(!BO || !LW, "the light-only reverse model carries B alone");
     extern __shared__ __align__(16) float smem[];
     const int tid = threadIdx.x, BS = blockDim.x;
     const int band = blockIdx.x % a.nbands;
@@ -314,7 +317,10 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
                                  fmaf(fo.y, pB, 2.0f * fo.z * pB * pV), 2.0f * fo.z * pB * pS,
                                  -fo.w * pB * il * il);
             }
-            point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
+            if (BO)
+                point_model_adj_b<BULGE, NDISC>(tc, T, du, dv, fo.x, ad);
+            else
+                point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
         }
         if (rA + RS < rend) load_rows(rA + RS);     // the next phase's new pixel rows
         __syncthreads();
@@ -365,8 +371,24 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
 }
 
 template <int LW, int KH>
-hipError_t launch_adj_lw(int bulge, int nd, int halo, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+hipError_t launch_adj_lw(int bulge, int nd, int halo, int bonly, dim3 grid, dim3 block, size_t lds, hipStream_t st,
                          const AdjArgs& a) {
+#if GK_LW == 0
+    if (bonly) {                // light-only reverse model: the halo does not enter B
+#define GK_BALAUNCH(BU, ND)                                                                     \
+        if (bulge == BU && nd == ND) {                                                          \
+            hipLaunchKernelGGL((adj_kernel<BU, ND, 0, LW, KH, 1>), grid, block, lds, st, a);   \
+            return hipGetLastError();                                                           \
+        }
+        GK_BALAUNCH(1, 0) GK_BALAUNCH(1, 1) GK_BALAUNCH(1, 2)
+        GK_BALAUNCH(2, 0) GK_BALAUNCH(2, 1) GK_BALAUNCH(2, 2)
+        GK_BALAUNCH(0, 1) GK_BALAUNCH(0, 2)
+#undef GK_BALAUNCH
+        return hipErrorInvalidValue;
+    }
+#else
+    if (bonly) return hipErrorInvalidValue;
+#endif
 #define GK_ALAUNCH(BU, ND, HA)                                                          \
     if (bulge == BU && nd == ND && halo == HA) {                                         \
         hipLaunchKernelGGL((adj_kernel<BU, ND, HA, LW, KH>), grid, block, lds, st, a);  \
@@ -384,6 +406,6 @@ hipError_t launch_adj_lw(int bulge, int nd, int halo, dim3 grid, dim3 block, siz
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_adj_lw<GK_LW, GK_KH>(int, int, int, dim3, dim3, size_t, hipStream_t, const AdjArgs&);
+template hipError_t launch_adj_lw<GK_LW, GK_KH>(int, int, int, int, dim3, dim3, size_t, hipStream_t, const AdjArgs&);
 
 }  // namespace gk

@@ -1075,12 +1075,13 @@ static int run_grad(gk_grid* g, const double* theta, int B, int stride, double* 
         const dim3 grid2((unsigned)(n * aa.nbands)), block2(ADJ_BS);
         const bool kh4 = g->adj_KP == 8;
         const int bu = g->d.bulge, nd = g->d.n_discs, ha = g->d.halo;
+        const int bonly = !g->geo.lw && g->map_mask == 1;     // only B has valid pixels
         if (g->geo.lw)
-            e = kh4 ? launch_adj_lw<1, 4>(bu, nd, ha, grid2, block2, g->adj_lds, st, aa)
-                    : launch_adj_lw<1, 6>(bu, nd, ha, grid2, block2, g->adj_lds, st, aa);
+            e = kh4 ? launch_adj_lw<1, 4>(bu, nd, ha, 0, grid2, block2, g->adj_lds, st, aa)
+                    : launch_adj_lw<1, 6>(bu, nd, ha, 0, grid2, block2, g->adj_lds, st, aa);
         else
-            e = kh4 ? launch_adj_lw<0, 4>(bu, nd, ha, grid2, block2, g->adj_lds, st, aa)
-                    : launch_adj_lw<0, 6>(bu, nd, ha, grid2, block2, g->adj_lds, st, aa);
+            e = kh4 ? launch_adj_lw<0, 4>(bu, nd, ha, bonly, grid2, block2, g->adj_lds, st, aa)
+                    : launch_adj_lw<0, 6>(bu, nd, ha, bonly, grid2, block2, g->adj_lds, st, aa);
         if (e != hipSuccess) return fail(GK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
     }
     return GK_OK;

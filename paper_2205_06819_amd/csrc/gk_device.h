@@ -592,4 +592,88 @@ __device__ __forceinline__ void point_model_adj(const TC& c, const Tabs& T, floa
     ad[C_VF] -= dvb;
 }
 
+// Reverse mode of point_model_b: the adjoint fB = d logL / dB at one lattice
+// point of a grid whose only valid map is B, accumulated into the adjoints
+// of the constants B depends on (frame, bulge Ab and 1/Rb, discs Ad and
+// -log2(e)/Rd); the other constants' adjoints are untouched.
+template <bool JF>
+__device__ __forceinline__ float eval_g_d(const float4* __restrict__ T, float s, float& dg) {
+    if (s < 4096.0f) {
+        float u;
+        const int k = piece(s, GK_S_ELO, u);
+        const float v = horner8d(T[4 * k], T[4 * k + 1], u, dg);
+        dg *= piece_dudx(s);
+        return v;
+    }
+    const float w = frcp(s), w2 = w * w, w3 = w2 * w;
+    const Dual pg = tail_g<JF>(Dual{w, 1.0f});              // s^3 g = Pg(w), w = 1/s
+    dg = -w3 * w * (3.0f * pg.v + w * pg.d);
+    return w3 * pg.v;
+}
+
+template <int BULGE, int NDISC>
+__device__ __forceinline__ void point_model_adj_b(const TC& c, const Tabs& T, float du, float dv, float fB,
+                                                  float (&ad)[NCONST]) {
+    const float xp = fmaf(du, c.ca, dv * c.sa);
+    const float yp = fmaf(dv, c.ca, -du * c.sa);
+    const float x2 = xp * xp, y2 = yp * yp;
+    float r = 0.0f, r2 = 0.0f, rinv = 0.0f;
+    if (NDISC > 0) {
+        r2 = fmaf(y2, c.sec2i, x2);
+        rinv = r2 > 0.0f ? frsq(r2) : 0.0f;
+        r = r2 * rinv;
+    }
+    float scale = 1.0f, eref = 0.0f;
+    if (!BULGE && NDISC > 0) {
+        eref = r * c.nl2Rd[0];
+        if (NDISC > 1) eref = fmaxf(eref, r * c.nl2Rd[1]);
+        scale = fexp2(eref);
+    }
+    // B = scale (Ab g(R / Rb) + sum_j Ad_j 2^(r nl2Rd_j - eref)); eref cancels
+    const float Btb = fB * scale;
+    float rb = 0.0f, x2b = 0.0f, y2b = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NDISC; ++j) {
+        const int o = C_D0 + 7 * j;
+        const float ex = fexp2(fmaf(r, c.nl2Rd[j], -eref));
+        ad[o + 1] = fmaf(Btb, ex, ad[o + 1]);
+        const float argb = Btb * c.Ad[j] * ex * 0.69314718f;
+        rb = fmaf(argb, c.nl2Rd[j], rb);
+        ad[o + 0] = fmaf(argb, r, ad[o + 0]);
+    }
+    if (BULGE) {
+        const float R = fsqrt(fmaf(xp, xp, y2));
+        const float sbr = R * c.invRb;
+        const bool clamped = !(sbr > S_MIN);
+        float dg;
+        const float g = eval_g_d<BULGE == 2>(T.gh, clamped ? S_MIN : sbr, dg);
+        ad[C_AB] = fmaf(Btb, g, ad[C_AB]);
+        if (!clamped) {
+            const float sbb = Btb * c.Ab * dg;
+            ad[C_INVRB] = fmaf(sbb, R, ad[C_INVRB]);
+            if (R > 0.0f) {
+                const float t2 = sbb * c.invRb * 0.5f * frcp(R);
+                x2b += t2;
+                y2b += t2;
+            }
+        }
+    }
+    if (NDISC > 0 && r2 > 0.0f) {
+        // r = r2 rinv, rinv = r2^-1/2, r2 = y2 sec2i + x2
+        const float rinvb = rb * r2;
+        const float r2b = fmaf(rb, rinv, -0.5f * rinvb * rinv * rinv * rinv);
+        y2b = fmaf(r2b, c.sec2i, y2b);
+        ad[C_SEC2I] = fmaf(r2b, y2, ad[C_SEC2I]);
+        x2b += r2b;
+    }
+    const float xpb = 2.0f * xp * x2b;
+    const float ypb = 2.0f * yp * y2b;
+    ad[C_CA] = fmaf(xpb, du, fmaf(ypb, dv, ad[C_CA]));
+    ad[C_SA] = fmaf(xpb, dv, fmaf(-ypb, du, ad[C_SA]));
+    const float dub = fmaf(xpb, c.ca, -ypb * c.sa);
+    const float dvb = fmaf(xpb, c.sa, ypb * c.ca);
+    ad[C_UF] -= dub;
+    ad[C_VF] -= dvb;
+}
+
 }  // namespace gk

@@ -158,8 +158,10 @@ hipError_t launch_fwd(int bulge, int ndisc, int halo, int bonly, dim3 grid, dim3
 template <int LW>
 hipError_t launch_multi(dim3 grid, dim3 block, size_t lds, hipStream_t st, const FwdArgs* grids, const int4* items,
                         const double* theta, int stride, double* logL);
+// bonly: the light-only reverse model (a grid whose only valid map is B; map
+// averaging only, else hipErrorInvalidValue)
 template <int LW, int KH>
-hipError_t launch_adj_lw(int bulge, int ndisc, int halo, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+hipError_t launch_adj_lw(int bulge, int ndisc, int halo, int bonly, dim3 grid, dim3 block, size_t lds, hipStream_t st,
                          const AdjArgs& a);
 
 }  // namespace gk
