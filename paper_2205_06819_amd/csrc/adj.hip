@@ -40,6 +40,20 @@
 
 namespace gk {
 
+// The pixel adjoints travel as one float4 per pixel (the four maps) or, for a
+// grid whose only valid map is B, as one float.
+template <int BO> struct AdjVec { using T = float4; };
+template <> struct AdjVec<1> { using T = float; };
+__device__ __forceinline__ void vzero(float4& v) { v = make_float4(0.f, 0.f, 0.f, 0.f); }
+__device__ __forceinline__ void vzero(float& v) { v = 0.0f; }
+__device__ __forceinline__ void vfma(float w, const float4& v, float4& acc) {
+    acc.x = fmaf(w, v.x, acc.x);
+    acc.y = fmaf(w, v.y, acc.y);
+    acc.z = fmaf(w, v.z, acc.z);
+    acc.w = fmaf(w, v.w, acc.w);
+}
+__device__ __forceinline__ void vfma(float w, float v, float& acc) { acc = fmaf(w, v, acc); }
+
 // Chain rule from the adjoints of the FP32 constants of make_tc to the
 // parameters (FP64), then writes the gradient row (zeros past P), or adds it
 // to the row (accum; the padding columns are left alone).
@@ -143,8 +157,9 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     const int RS = a.rows, NLEV = a.nlev, NCP = NC + 2 * D, RB = a.rb;
     const AdjLayout L = adj_layout(a.band_h, a.band_w, s, pad, D, RS, NLEV, RB, 2 * KH);
     float* s_tab = smem + L.tab;
-    float4* s_ring = (float4*)(smem + L.ring);      // [RB][NC]
-    float4* s_S = (float4*)(smem + L.S);            // [RS][NCP][NLEV]
+    using V = typename AdjVec<BO>::T;               // four maps, or B alone
+    V* s_ring = (V*)(smem + L.ring);                // [RB][NC]
+    V* s_S = (V*)(smem + L.S);                      // [RS][NCP][NLEV]
     const int4* s_ht = (const int4*)(smem + L.ht);  // [s][s][KH]
     const int2* s_vt = (const int2*)(smem + L.vt);  // [s][DSTRIDE]
     double* s_red = (double*)(smem + L.red);
@@ -171,7 +186,8 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
         int* vt = (int*)(smem + L.vt);
         const int* gvt = (const int*)a.vt;
         for (int i = tid; i < s * DSTRIDE * 2; i += BS) vt[i] = gvt[i];
-        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        V z;
+        vzero(z);
         for (int i = tid; i < RB * NC; i += BS) s_ring[i] = z;
         for (int i = tid; i < RS * NCP * NLEV; i += BS) s_S[i] = z;
         for (int i = tid; i < NR; i += BS) s_span[i] = a.span[jf0 + i];
@@ -227,10 +243,14 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
         for (int p = tid; p < nnew * NC; p += BS) {
             const int k = (int)(((float)p + 0.5f) * inv_nc), cc = p - k * NC;
             const int jj = loaded + 1 + k;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            V v;
+            vzero(v);
             if (jj < NR) {
                 const size_t pix = (size_t)(jf0 + jj) * G.nx + cf0 + cc;
-                v = make_float4(fb[pix], fb[mstr + pix], fb[2 * mstr + pix], fb[3 * mstr + pix]);
+                if constexpr (BO)
+                    v = fb[pix];
+                else
+                    v = make_float4(fb[pix], fb[mstr + pix], fb[2 * mstr + pix], fb[3 * mstr + pix]);
             }
             int slot = base_n + jj - (qlo_n - D);
             slot = slot >= RB ? slot - RB : slot;
@@ -252,28 +272,25 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             const int r = rA + rl;
             const int qr = (int)(((float)r + 0.5f) * inv_s), ph = r - qr * s;
             const int2* vt = s_vt + ph * DSTRIDE;
-            float4* Sp = s_S + ((size_t)rl * NCP + cc + D) * NLEV;
+            V* Sp = s_S + ((size_t)rl * NCP + cc + D) * NLEV;
             const int off0 = base + qr - qlo + D;       // ring position of pixel row qr, unwrapped
             // all DSTRIDE entries (zero past the phase's lags: weight 0, no
             // store), so that the table and ring loads issue together
             int2 e[DSTRIDE];
 #pragma unroll
             for (int n = 0; n < DSTRIDE; ++n) e[n] = vt[n];
-            float4 v[DSTRIDE];
+            V v[DSTRIDE];
 #pragma unroll
             for (int n = 0; n < DSTRIDE; ++n) {
                 int slot = off0 - (e[n].x & 255);
                 slot = slot >= RB ? slot - RB : slot;
                 v[n] = s_ring[slot * NC + cc];
             }
-            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+            V acc;
+            vzero(acc);
 #pragma unroll
             for (int n = 0; n < DSTRIDE; ++n) {
-                const float w = __int_as_float(e[n].y);
-                acc.x = fmaf(w, v[n].x, acc.x);
-                acc.y = fmaf(w, v[n].y, acc.y);
-                acc.z = fmaf(w, v[n].z, acc.z);
-                acc.w = fmaf(w, v[n].w, acc.w);
+                vfma(__int_as_float(e[n].y), v[n], acc);
                 if (e[n].x >> 16) Sp[(e[n].x >> 8) & 255] = acc;
             }
         }
@@ -288,39 +305,38 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             const int x = plo + (qq - rl * pw);
             const int qr = (int)(((float)(rA + rl) + 0.5f) * inv_s), ph = rA + rl - qr * s;
             const int qx = (int)(((float)x + 0.5f) * inv_s), ix = x - qx * s;
-            const float4* Sb = s_S + ((size_t)rl * NCP + qx + D) * NLEV;
+            const V* Sb = s_S + ((size_t)rl * NCP + qx + D) * NLEV;
             const int4* h = s_ht + (ph * s + ix) * KH;
             int4 e[KH];
 #pragma unroll
             for (int k2 = 0; k2 < KH; ++k2) e[k2] = h[k2];
-            float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+            V f;
+            vzero(f);
 #pragma unroll
             for (int k2 = 0; k2 < KH; ++k2) {
-                const float4 v0 = Sb[e[k2].x], v1 = Sb[e[k2].z];
-                const float w0 = __int_as_float(e[k2].y), w1 = __int_as_float(e[k2].w);
-                f.x = fmaf(w1, v1.x, fmaf(w0, v0.x, f.x));
-                f.y = fmaf(w1, v1.y, fmaf(w0, v0.y, f.y));
-                f.z = fmaf(w1, v1.z, fmaf(w0, v0.z, f.z));
-                f.w = fmaf(w1, v1.w, fmaf(w0, v0.w, f.w));
+                const V v0 = Sb[e[k2].x], v1 = Sb[e[k2].z];
+                vfma(__int_as_float(e[k2].y), v0, f);
+                vfma(__int_as_float(e[k2].w), v1, f);
             }
             const int r = rA + rl;
             const float du = (float)(ubase + x - tc.Ui) - tc.Uf;
             const float dv = (float)(vlo + r - tc.Vi) - tc.Vf;
-            float4 fo = make_float4(f.x * invW, f.y * invW, f.z * invW, f.w * invW);
-            if (LW) {
-                // the lattice carries (B, B v, B (sigma^2 + v^2), B / <L/M>): map their
-                // adjoints to those of (B, v, sigma, <L/M>) at this point
-                float pB, pV, pS, pL;
-                point_model<BULGE, NDISC, HALO>(tc, T, du, dv, pB, pV, pS, pL);
-                const float il = frcp(pL);
-                fo = make_float4(fo.x + fo.y * pV + fo.z * fmaf(pS, pS, pV * pV) + fo.w * il,
-                                 fmaf(fo.y, pB, 2.0f * fo.z * pB * pV), 2.0f * fo.z * pB * pS,
-                                 -fo.w * pB * il * il);
-            }
-            if (BO)
-                point_model_adj_b<BULGE, NDISC>(tc, T, du, dv, fo.x, ad);
-            else
+            if constexpr (BO) {
+                point_model_adj_b<BULGE, NDISC>(tc, T, du, dv, f * invW, ad);
+            } else {
+                float4 fo = make_float4(f.x * invW, f.y * invW, f.z * invW, f.w * invW);
+                if (LW) {
+                    // the lattice carries (B, B v, B (sigma^2 + v^2), B / <L/M>): map their
+                    // adjoints to those of (B, v, sigma, <L/M>) at this point
+                    float pB, pV, pS, pL;
+                    point_model<BULGE, NDISC, HALO>(tc, T, du, dv, pB, pV, pS, pL);
+                    const float il = frcp(pL);
+                    fo = make_float4(fo.x + fo.y * pV + fo.z * fmaf(pS, pS, pV * pV) + fo.w * il,
+                                     fmaf(fo.y, pB, 2.0f * fo.z * pB * pV), 2.0f * fo.z * pB * pS,
+                                     -fo.w * pB * il * il);
+                }
                 point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
+            }
         }
         if (rA + RS < rend) load_rows(rA + RS);     // the next phase's new pixel rows
         __syncthreads();
