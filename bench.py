@@ -789,7 +789,7 @@ def run_single(args, name, *, steps, warmup, grad_steps, hmc_steps, plain, with_
         roof_adj = {"bound": "alu", "achieved": round(a_ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(a_ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
                     "frac_of_nonpacked_fp32": round(a_ach / PEAK_FP32_NONPACKED, 4),
-                    "kernel": f"gk::adj_kernel<{spec.bulge},{spec.n_discs},{spec.halo},{lw},{adjoint_tap_pairs(spec)}>",
+                    "kernel": f"gk::adj_kernel<{spec.bulge},{spec.n_discs},{spec.halo},{lw},{adjoint_tap_pairs(spec)},0>",
                     "kernel_ms": round(ms_adj, 4),
                     "kernel_ms_from": "gradient step minus forward step (HIP events)",
                     "flop_per_vector": n_need * fa,
