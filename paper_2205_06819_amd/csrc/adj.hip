@@ -232,7 +232,9 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     const float* fb = a.fbar + (size_t)b * 4 * mstr;
     // Pixel rows of rbar enter a ring of RB rows, slot = row mod RB.  The rows
     // a phase reaches are loaded during the previous phase's gather (the ring
-    // is not read then), so a phase needs two barriers.
+    // is not read then), so a phase needs two barriers: when they fit one per
+    // thread, their global loads are issued before that gather and stored to
+    // the ring after it, so that the gather hides their latency.
     // the first phase reaches pixel rows from rbeg / s - D on
     int loaded = max(-1, rbeg / s - D - 1);         // last pixel row put in the ring
     auto load_rows = [&](int rA_next) {
@@ -295,6 +297,38 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             }
         }
         __syncthreads();
+        // ---- the next phase's new pixel rows: global loads issued now
+        const bool more = rA + RS < rend;
+        bool pf_sync = false;
+        int pf_at = -1;
+        V pf_v;
+        vzero(pf_v);
+        if (more) {
+            const int rA_next = rA + RS;
+            const int nrow_n = min(RS, rend - rA_next);
+            const int qlo_n = rA_next / s, qhi_n = (rA_next + nrow_n - 1) / s;
+            const int base_n = ((qlo_n - D) % RB + RB) % RB;
+            const int nnew = qhi_n - loaded;
+            if (nnew * NC <= BS) {
+                if (tid < nnew * NC) {
+                    const int k = (int)(((float)tid + 0.5f) * inv_nc), cc = tid - k * NC;
+                    const int jj = loaded + 1 + k;
+                    if (jj < NR) {
+                        const size_t pix = (size_t)(jf0 + jj) * G.nx + cf0 + cc;
+                        if constexpr (BO)
+                            pf_v = fb[pix];
+                        else
+                            pf_v = make_float4(fb[pix], fb[mstr + pix], fb[2 * mstr + pix], fb[3 * mstr + pix]);
+                    }
+                    int slot = base_n + jj - (qlo_n - D);
+                    slot = slot >= RB ? slot - RB : slot;
+                    pf_at = slot * NC + cc;
+                }
+                loaded = max(loaded, qhi_n);
+            } else {
+                pf_sync = true;
+            }
+        }
         // ---- horizontal gather and reverse point model, flat over the phase's points
         const int prange = s_prange[ph_i];
         const int plo = prange & 0xffff, pw = prange >> 16;
@@ -338,7 +372,8 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
                 point_model_adj<BULGE, NDISC, HALO>(tc, T, du, dv, fo.x, fo.y, fo.z, fo.w, ad);
             }
         }
-        if (rA + RS < rend) load_rows(rA + RS);     // the next phase's new pixel rows
+        if (pf_sync) load_rows(rA + RS);            // too many rows to prefetch in registers
+        if (pf_at >= 0) s_ring[pf_at] = pf_v;
         __syncthreads();
     }
 
