@@ -47,6 +47,10 @@ SPECS = {
     "one_row": W.GridSpec(17, 1, 0.2, 3, 0.8, 1, 2, W.HALO_NFW),
     "one_column": W.GridSpec(1, 13, 0.2, 1, 1.2, 0, 1, W.HALO_HERNQUIST),
     "widest_stencil": W.GridSpec(12, 9, 0.15, 5, W.SIGMA_FWHM_4, 1, 2, W.HALO_NFW),
+    # extreme aspect ratios: many ragged column bands of three rows, one
+    # column band of many rows (forward bands and adjoint lattice blocks)
+    "long_strip": W.GridSpec(257, 3, 0.2, 3, W.SIGMA_FWHM_2P5, 1, 2, W.HALO_NFW),
+    "tall_strip": W.GridSpec(2, 263, 0.15, 1, 1.5, W.BULGE_JAFFE, 1, W.HALO_HERNQUIST),
 }
 
 
