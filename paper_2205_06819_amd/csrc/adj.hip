@@ -1,6 +1,8 @@
 // Adjoint of the likelihood: d logL / d theta from the forward pass's
 // per-pixel adjoints rbar = d logL / d F (written by the forward kernel in its
-// adjoint-seed mode), compiled once per PSF mode (-DGK_LW=0|1).
+// adjoint-seed mode), compiled once per PSF mode and horizontal tap-pair
+// count (-DGK_LW=0|1 -DGK_KH=4|6); the map-averaging units also carry the
+// light-only variant for grids whose only valid map is B.
 //
 // One workgroup = one parameter vector x one block of the padded lattice.
 // The gradient is the sum, over pixels p and maps m, of rbar_m(p)
@@ -17,7 +19,8 @@
 // independent of s):
 //
 //   ring       the pixel rows of rbar the phase reaches (a ring of
-//              D + 1 + ceil((R - 1) / s) rows, new rows loaded per phase);
+//              D + 1 + ceil((R - 1) / s) rows; a phase's new rows are loaded
+//              while the previous phase's points are evaluated);
 //   vertical   per (lattice row, pixel column): running sums S_l of
 //              g(|b|) rbar over the pixel rows in reach, grouped by the
 //              stencil half-width A(|b|) (largest first);
