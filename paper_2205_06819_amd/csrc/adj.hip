@@ -30,8 +30,11 @@
 //              built on the host), then the reverse point model into 27 FP32
 //              adjoints of the per-theta constants.
 //
-// The constant adjoints are summed in FP64 (waves, then bands in order, by
-// the last workgroup of the vector), and the chain rule to theta runs once.
+// The special-function tables are read from constant memory through the
+// vector L1 cache (the luminosity-weighted body, which evaluates the model
+// twice per point, copies them to LDS instead).  The constant adjoints are
+// summed in FP64 (waves, then bands in order, by the last workgroup of the
+// vector), and the chain rule to theta runs once.
 #include "gk_fwd.h"
 
 #ifndef GK_LW
@@ -158,8 +161,8 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
     const int xbeg = max(0, Lc0 - cf0 * s), xend = Lc1 - cf0 * s;
     const int vlo = jf0 * s + hs, ubase = cf0 * s + hs;
     const int RS = a.rows, NLEV = a.nlev, NCP = NC + 2 * D, RB = a.rb;
-    const AdjLayout L = adj_layout(a.band_h, a.band_w, s, pad, D, RS, NLEV, RB, 2 * KH);
-    float* s_tab = smem + L.tab;
+    const AdjLayout L = adj_layout(a.band_h, a.band_w, s, pad, D, RS, NLEV, RB, 2 * KH, LW);
+    float* s_tab = smem + L.tab;                    // the LW body's copy of the tables
     using V = typename AdjVec<BO>::T;               // four maps, or B alone
     V* s_ring = (V*)(smem + L.ring);                // [RB][NC]
     V* s_S = (V*)(smem + L.S);                      // [RS][NCP][NLEV]
@@ -177,12 +180,15 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
             for (int q = tid; q < a.stride; q += BS) a.grad[(size_t)b * a.stride + q] = 0.0;
         return;
     }
-    // ---- prologue: tables, zeroed ring and S buffer, row spans
+    // ---- prologue: tables (LW), zeroed ring and S buffer, row spans
     {
-        const float* tgh = BULGE == 2 ? gk_tab_jgh : gk_tab_gh;
-        for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = tgh[i];
-        for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
-        for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
+        if constexpr (LW != 0) {
+            const Tabs C = const_tabs<BULGE>();
+            const float* tgh = (const float*)C.gh;
+            for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = tgh[i];
+            for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
+            for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
+        }
         int* ht = (int*)(smem + L.ht);
         const int* ght = (const int*)a.ht;
         for (int i = tid; i < s * s * KH * 4; i += BS) ht[i] = ght[i];
@@ -223,8 +229,9 @@ __global__ void __launch_bounds__(ADJ_BS) adj_kernel(AdjArgs a) {
         // frame columns < 2^15 (band_w <= 128, D <= 10, s <= 15): both fields fit
         s_prange[k] = hi >= lo ? lo | ((hi - lo + 1) << 16) : 0;
     }
-    const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
-                 (const float4*)(s_tab + TAB_GH + TAB_PHI)};
+    const Tabs T = LW ? Tabs{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
+                             (const float4*)(s_tab + TAB_GH + TAB_PHI)}
+                      : const_tabs<BULGE>();
     float ad[NCONST];
 #pragma unroll
     for (int k = 0; k < NCONST; ++k) ad[k] = 0.0f;

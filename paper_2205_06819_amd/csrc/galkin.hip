@@ -173,34 +173,33 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int 
 static void fit_shape(const gk_grid* g, int& bh, int& bw, int bs_fixed);
 
 static int default_rules(gk_grid* g) {
-    // Large batches: bands of up to 40 x 40 pixels (measured best on the 3x3
+    // Large batches: bands of up to 80 x 40 pixels (measured best on the 3x3
     // lattice: enough workgroups per CU to overlap one band's model phase with
     // another's stencil phase).  Small batches: small square bands so that one
     // theta spreads over many CUs.
     const int nx = g->d.nx, ny = g->d.ny;
     g->rules.clear();
-    // the grid split into near-equal bands of at most 40 pixels each way; a
-    // wide PSF on a coarse lattice (lag D >= 9 pixel rows, e.g. no
-    // supersampling, or 5x5 supersampling of a 4 px FWHM) spends D of every
-    // band_h + D steps filling the lag and recomputes a 2 pad halo, so there
-    // bands grow to 32 D rows and 64 columns (measured 1.4x faster on a
-    // 160 x 160 grid with D = 10; on the 300 x 300, s = 5 grid 300 x 64 bands
-    // take 154.2 ms per 8192 vectors against 162.7 for 150 x 60); a grid with
-    // at least four full 64-pixel bands uses exactly 64 columns, so that the
-    // stencil phase's 4 x 64 threads are whole waves (the narrower last band
-    // costs less; with fewer bands an even split measured faster)
-    // (the luminosity-weighted mode, whose phases end in a moment exchange,
-    // prefers 80-row bands: measured 6 % faster on the realistic cube)
-    const int hmax = g->D >= 9 ? 32 * g->D : (g->geo.lw ? 80 : 40), wmax = g->D >= 9 ? 64 : 40;
+    // the grid split into near-equal bands of at most 80 rows and 40 columns
+    // (on the 80 x 80 realistic cube 0.556 ms per 1024 vectors against 0.582
+    // for 40 x 40 bands; the luminosity-weighted mode, whose phases end in a
+    // moment exchange, 0.583 against 0.606); a wide PSF on a coarse lattice
+    // (lag D >= 9 pixel rows, e.g. no supersampling, or 5x5 supersampling of a
+    // 4 px FWHM) spends D of every band_h + D steps filling the lag and
+    // recomputes a 2 pad halo, so there bands grow to 32 D rows and 64 columns
+    // (measured 1.4x faster on a 160 x 160 grid with D = 10; on the 300 x 300,
+    // s = 5 grid 300 x 64 bands take 139.7 ms per 8192 vectors against 143.6
+    // for 150 x 64 and 154.8 for 300 x 50); a grid with at least four full
+    // 64-pixel bands uses exactly 64 columns, so that the stencil phase's
+    // 4 x 64 threads are whole waves (the narrower last band costs less; with
+    // fewer bands an even split measured faster)
+    const int hmax = g->D >= 9 ? 32 * g->D : 80, wmax = g->D >= 9 ? 64 : 40;
     int bh = (ny + (ny + hmax - 1) / hmax - 1) / ((ny + hmax - 1) / hmax);
     int bw = (nx + (nx + wmax - 1) / wmax - 1) / ((nx + wmax - 1) / wmax);
     if (g->D >= 9 && nx >= 4 * 64) bw = 64;
     fit_shape(g, bh, bw, 0);
-    // on the 3x3 lattice two pixel rows (six lattice rows) per model phase: the
-    // smaller row buffer leaves LDS for a fifth workgroup per CU (measured 6 %
-    // faster than three rows on the 80 x 80 realistic cube)
-    const int steps_big = g->geo.s == 3 ? 2 : 0;
-    g->rules.push_back({512, bh, bw, steps_big});
+    // pixel-row steps per model phase: make_cfg's default (three on the 3x3
+    // lattice: 0.556 ms against 0.570 for two on the realistic cube)
+    g->rules.push_back({512, bh, bw, 0});
     // >= 4096 vectors fill the chip without splitting a grid finely: bands of
     // up to 128 rows and 64 columns recompute less of the stencil halo
     // (measured 1.45x faster than 34 x 34 bands on a 100 x 100 grid, B = 4096)
@@ -209,7 +208,7 @@ static int default_rules(gk_grid* g) {
         int bh2 = (ny + (ny + hb - 1) / hb - 1) / ((ny + hb - 1) / hb);
         int bw2 = (nx + (nx + wb - 1) / wb - 1) / ((nx + wb - 1) / wb);
         fit_shape(g, bh2, bw2, 0);
-        g->rules.push_back({4096, bh2, bw2, steps_big});
+        g->rules.push_back({4096, bh2, bw2, 0});
     }
     int side = std::max(4, (int)std::ceil(std::sqrt((double)nx * ny / 64.0)));
     bh = std::min(ny, side), bw = std::min(nx, side);
@@ -233,7 +232,8 @@ constexpr int ADJ_LDS_3 = 53 * 1024;
 static int adj_ring_rows(const gk_grid* g, int rows) { return g->D + 1 + (rows - 1 + g->geo.s - 1) / g->geo.s; }
 
 static int adj_lds_of(const gk_grid* g, int bh, int bw, int rows) {
-    return adj_layout(bh, bw, g->geo.s, g->geo.pad, g->D, rows, g->adj_nlev, adj_ring_rows(g, rows), g->adj_KP)
+    return adj_layout(bh, bw, g->geo.s, g->geo.pad, g->D, rows, g->adj_nlev, adj_ring_rows(g, rows), g->adj_KP,
+                      g->geo.lw != 0)
         .total_bytes;
 }
 
@@ -296,24 +296,28 @@ static int set_adj_shape(gk_grid* g, int bh, int bw, int rows) {
     return GK_OK;
 }
 
-// Default adjoint shape (measured on the 80 x 80, 100 x 100 and 300 x 300
-// benchmark grids).  A band's block reads a halo of D + 1 pixel columns and
-// rows and restarts its ring, so wide and tall bands are cheapest: widths
-// from even splits of the columns (at most 80) and from 256 / (s r) (a phase
-// of r lattice rows then fills the threads once), widest first, then bands of
-// up to 128 rows (taller if the grid would need more than MAX_BANDS_ADJ
-// bands), while a vector still spans at least two bands (more workgroups).
-// Rows per phase: the most, up to 3, that keep >= 85 % of the threads busy
-// (fewer phases, each with two barriers and a dependent chain of LDS reads)
-// within the LDS that leaves room for three workgroups per CU.  A grid whose
-// adjoint fits no shape keeps adj_nbands = 0: its forward calls work and its
-// gradient calls return GK_EINVAL.
+// Default adjoint shape (measured on the 80 x 80, 160 x 160 and 300 x 300
+// benchmark grids).  Rows per phase matter most: each phase costs two
+// barriers and a vertical pass over the frame's columns, so the rule takes
+// the most rows, up to 3, that keep >= 85 % of the threads busy within the
+// LDS that leaves room for three workgroups per CU (on the 300 x 300 grid 3
+// rows per phase take about 30 % less time than 1).  For that row count, a band's
+// block reads a halo of D + 1 pixel columns and rows and restarts its ring,
+// so wide and tall bands are cheapest: widths from even splits of the
+// columns (at most 128, the kernel's limit, and at least 4 (D + 1) so that
+// the halo stays within a quarter of the band) and from 256 / (s r) (a phase
+// of r lattice rows then fills the threads once), widest first, then the
+// tallest bands for which a vector still spans at least two bands (more
+// workgroups) and the grid at most MAX_BANDS_ADJ bands (on a 100 x 100 grid,
+// B = 4096, bands of 50 x 100 pixels take 0.94 of the time of 100 x 50).  A grid whose adjoint fits no shape keeps
+// adj_nbands = 0: its forward calls work and its gradient calls return
+// GK_EINVAL.
 static int default_adj_shape(gk_grid* g) {
     const int nx = g->d.nx, ny = g->d.ny, s = g->geo.s;
     const std::string saved = g_err;
     auto split = [](int n, int m) { const int k = (n + m - 1) / m; return (n + k - 1) / k; };
     std::vector<int> widths;
-    for (int m : {80, 64, 40, 32, 20, 16, 8}) widths.push_back(split(nx, m));
+    for (int m : {128, 80, 64, 40, 32, 20, 16, 8}) widths.push_back(split(nx, m));
     for (int r = 1; r <= 4; ++r)
         if (256 / (s * r) >= 8) widths.push_back(std::min(nx, 256 / (s * r)));
     std::sort(widths.begin(), widths.end(), [](int x, int y) { return x > y; });
@@ -326,20 +330,16 @@ static int default_adj_shape(gk_grid* g) {
     };
     for (int cap : {ADJ_LDS_3, ADJ_LDS_MAX})
         for (int pass = 0; pass < 2; ++pass)        // pass 1: single-band shapes allowed
-            for (int bw : widths) {
-                if (bw > 80) continue;
-                for (int hmax : {128, 64, 256, 512, 1024, 2048, 4096}) {
-                    const int bh = split(ny, hmax);
-                    const int nb = ((nx + bw - 1) / bw) * ((ny + bh - 1) / bh);
-                    if (nb > MAX_BANDS_ADJ || (pass == 0 && big && nb < 2)) continue;
-                    int rows = 0;
-                    for (int r = 1; r <= 3; ++r) {
-                        if (adj_lds_of(g, bh, bw, r) > cap) break;
-                        if (adj_fill(g, bw, r) >= 0.85) rows = r;
+            for (int rows = 3; rows >= 1; --rows)
+                for (int bw : widths) {
+                    if (bw > 128 || (bw < 4 * (g->D + 1) && bw < nx) || adj_fill(g, bw, rows) < 0.85) continue;
+                    for (int hmax : {4096, 2048, 1024, 512, 256, 128, 64}) {
+                        const int bh = split(ny, hmax);
+                        const int nb = ((nx + bw - 1) / bw) * ((ny + bh - 1) / bh);
+                        if (nb > MAX_BANDS_ADJ || (pass == 0 && big && nb < 2)) continue;
+                        if (adj_lds_of(g, bh, bw, rows) <= cap && try_set(bh, bw, rows)) return GK_OK;
                     }
-                    if (rows && try_set(bh, bw, rows)) return GK_OK;
                 }
-            }
     // nothing reached the fill target: the best fill of the default heights
     for (int cap : {ADJ_LDS_3, ADJ_LDS_MAX})
         for (int hmax = 64; hmax <= 4096; hmax *= 2) {
@@ -367,6 +367,7 @@ static int default_adj_shape(gk_grid* g) {
 
 struct LaunchCfg {
     int band_h, band_w, nbx, nbands, BS, gsub, xw, lds;
+    int lds_tab;    // with the LDS copy of the tables (many-grid kernel, luminosity-weighted seed pass)
 };
 
 static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int bs_fixed, int steps) {
@@ -385,19 +386,24 @@ static int make_cfg(const gk_grid* g, int band_h, int band_w, LaunchCfg& c, int 
     }
     c.xw = band_w * s + 2 * pad + 1;
     // pixel-row steps per model phase: about ten lattice rows (measured best on
-    // the 3x3 lattice with 40x40 bands), at most RS_CAP lattice rows, and the
-    // row buffer within ~40 KiB of LDS; an explicit count is honoured up to
-    // those limits
+    // the 3x3 lattice with 80x40 bands), at most RS_CAP lattice rows, the row
+    // buffer within ~40 KiB of LDS (64 KiB for an explicit count) and, with
+    // the LDS copy of the tables, within 80 KiB; an explicit count is honoured
+    // up to those limits
     const int nfrm = nfr_max(band_h, s, pad);
     int gs = steps > 0 ? steps : std::max(1, (10 + s / 2) / s);
     gs = std::min({gs, GSUB_CAP, std::max(1, RS_CAP / s)});
     const int lw = g->geo.lw;
-    while (gs > 1 && make_layout(gs * s, c.xw, nfrm, band_h, lw ? 8 * gs * band_w : 0).total_bytes >
-                         (steps > 0 ? 64 : 40) * 1024)
-        --gs;
+    auto lds_of = [&](int gsub, bool tab) {
+        return make_layout(gsub * s, c.xw, nfrm, band_h, lw ? 8 * gsub * band_w : 0, tab).total_bytes;
+    };
+    while (gs > 1 && (lds_of(gs, false) > (steps > 0 ? 64 : 40) * 1024 || lds_of(gs, true) > 80 * 1024)) --gs;
     c.gsub = gs;
-    c.lds = make_layout(gs * s, c.xw, nfrm, band_h, lw ? 8 * gs * band_w : 0).total_bytes;
+    c.lds = lds_of(gs, false);
+    c.lds_tab = lds_of(gs, true);
     if (c.lds > 64 * 1024) return fail(GK_EINVAL, "launch shape needs %d bytes of LDS (> 64 KiB)", c.lds);
+    if (c.lds_tab > 80 * 1024)
+        return fail(GK_EINVAL, "launch shape needs %d bytes of LDS with the tables (> 80 KiB)", c.lds_tab);
     return GK_OK;
 }
 
@@ -419,8 +425,9 @@ static hipError_t enqueue_fwd(const gk_grid* g, const LaunchCfg& c, FwdArgs& a, 
     const dim3 grid((unsigned)(B * c.nbands)), block((unsigned)c.BS);
     // a grid whose only valid map is B runs the light-only model
     const int bonly = MODE != MODE_MAPS && !a.geo.lw && a.map_mask == 1;
-    return a.geo.lw ? launch_fwd<MODE, 1>(g->d.bulge, g->d.n_discs, g->d.halo, 0, grid, block, c.lds, st, a)
-                    : launch_fwd<MODE, 0>(g->d.bulge, g->d.n_discs, g->d.halo, bonly, grid, block, c.lds, st, a);
+    const size_t lds = MODE == MODE_FBAR && a.geo.lw ? c.lds_tab : c.lds;
+    return a.geo.lw ? launch_fwd<MODE, 1>(g->d.bulge, g->d.n_discs, g->d.halo, 0, grid, block, lds, st, a)
+                    : launch_fwd<MODE, 0>(g->d.bulge, g->d.n_discs, g->d.halo, bonly, grid, block, lds, st, a);
 }
 
 static int check_call(const gk_grid* g, const double* theta, int B, int stride, const void* out) {
@@ -548,7 +555,7 @@ static int build_plan(int device, const gk_grid* const* grids, int n, const int*
         LaunchCfg c;
         int rc = make_cfg(g, bh, bw, c, MULTI_BS, st);
         if (rc) { free_plan(p); return rc; }
-        lds = std::max(lds, c.lds);
+        lds = std::max(lds, c.lds_tab);
         fill_args(g, c, args[i], nullptr, 0);
         for (int band = 0; band < c.nbands; ++band) {
             const double cost = band_cost(g, c, band);

@@ -1,7 +1,7 @@
 // Device-side building blocks of the galkin kernels (gfx950 / CDNA4).
 //
 // Per-theta constants (computed in FP64, stored as FP32), the FP32
-// special functions of the model (piecewise polynomials read from LDS), and
+// special functions of the model (piecewise polynomials in constant memory), and
 // the per-lattice-point model of the paper's Sec. 2.1-2.4 with its
 // reverse-mode derivative.
 #pragma once
@@ -18,7 +18,7 @@ constexpr double G_KPC = 4.300917270e-6;     // kpc (km/s)^2 / Msun
 constexpr double PI = 3.14159265358979323846;
 constexpr float S_MIN = 1.0e-6f;             // clamp of s = R / R_b at the centre
 
-// FP32 table sizes in floats (LDS copies)
+// FP32 table sizes in floats
 constexpr int TAB_GH = GK_GH_NPIECE * 16;
 constexpr int TAB_PHI = GK_PHI_NPIECE * 8;
 constexpr int TAB_M = GK_M_NPIECE * 8;
@@ -150,7 +150,7 @@ __device__ __forceinline__ TC uniform_tc(const TC& a) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 special functions (tables in LDS)
+// FP32 special functions (piecewise-polynomial tables)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -312,6 +312,14 @@ struct Tabs {
     const float4* phi;
     const float4* m;
 };
+
+// the constant-memory tables (read through the vector L1 cache: a lookup's
+// piece index varies across the lanes); one bulge kind per grid
+template <int BULGE>
+__device__ __forceinline__ Tabs const_tabs() {
+    return Tabs{(const float4*)(BULGE == 2 ? gk_tab_jgh : gk_tab_gh), (const float4*)gk_tab_phi,
+                (const float4*)gk_tab_m};
+}
 
 // out: B_tot [Lsun/pc^2], v_los [km/s], sigma_los [km/s], <L/M> [Lsun/Msun]
 template <int BULGE, int NDISC, int HALO>

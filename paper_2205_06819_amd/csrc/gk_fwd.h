@@ -54,17 +54,20 @@ __device__ __forceinline__ void stencil_sub(const float* __restrict__ L0, int rs
     acc[0] = con[0];
 }
 
-// One parameter vector (row b) on one band of one grid.  load_tables = false
-// when the caller already staged the special-function tables in LDS.  LW = 1:
+// One parameter vector (row b) on one band of one grid.  LW = 1:
 // the PSF averages luminosity-weighted moments (a compile-time switch, so the
 // map-averaging instantiations do not carry its registers).
 // BO = 1: the grid's only valid map is B (a photometric grid; never with
 // MODE_MAPS or LW): the model phase evaluates the surface brightness alone
 // (point_model_b, equal bit for bit to point_model's B) and leaves the other
 // three rows of the buffer at zero, which the stencil skips anyway.
-template <int BULGE, int NDISC, int HALO, int MODE, int LW, int BO = 0>
-__device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const int band, float* smem,
-                                         const bool load_tables) {
+// TL = 1: the special-function tables are copied to LDS (after the rest of
+// the layout) and read there; else they are read from constant memory
+// through the vector L1 cache.  The copy pays where the registers already
+// cap the occupancy that the LDS it takes would lower: the many-grid kernel
+// and the luminosity-weighted seed pass.
+template <int BULGE, int NDISC, int HALO, int MODE, int LW, int BO = 0, int TL = 0>
+__device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const int band, float* smem) {
     static_assert(!BO || (MODE != MODE_MAPS && !LW), "the light-only body computes B alone");
     const int tid = threadIdx.x, BS = blockDim.x;
     const GridGeom& G = a.geo;
@@ -78,7 +81,8 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     const int ubase = c0 * s + hs;                  // lattice column of local column 0
     const int nfrm = nfr_max(a.band_h, s, pad);
     const int RS = a.gsub * s;
-    const Layout L = make_layout(RS, a.xw, nfrm, a.band_h, LW ? 8 * a.gsub * a.band_w : 0);
+    constexpr bool TAB_LDS = TL != 0;
+    const Layout L = make_layout(RS, a.xw, nfrm, a.band_h, LW ? 8 * a.gsub * a.band_w : 0, TAB_LDS);
     float* s_tab = smem + L.tab;
     float* s_rows = smem + L.rows;
     double* s_red = (double*)(smem + L.red);
@@ -102,9 +106,10 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
         return;
     }
 
-    // --- prologue: tables, zeroed row buffer, row spans
-    if (load_tables) {
-        const float* tgh = BULGE == 2 ? gk_tab_jgh : gk_tab_gh;     // one bulge kind per grid
+    // --- prologue: tables (TAB_LDS), zeroed row buffer, row spans
+    if constexpr (TAB_LDS) {
+        const Tabs C = const_tabs<BULGE>();
+        const float* tgh = (const float*)C.gh;
         for (int i = tid; i < TAB_GH; i += BS) s_tab[i] = tgh[i];
         for (int i = tid; i < TAB_PHI; i += BS) s_tab[TAB_GH + i] = gk_tab_phi[i];
         for (int i = tid; i < TAB_M; i += BS) s_tab[TAB_GH + TAB_PHI + i] = gk_tab_m[i];
@@ -143,8 +148,9 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     }
     __syncthreads();
 
-    const Tabs T{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
-                 (const float4*)(s_tab + TAB_GH + TAB_PHI)};
+    const Tabs T = TAB_LDS ? Tabs{(const float4*)s_tab, (const float4*)(s_tab + TAB_GH),
+                                  (const float4*)(s_tab + TAB_GH + TAB_PHI)}
+                           : const_tabs<BULGE>();
     const float invW = a.invW;
     double chi2 = 0.0;
     const size_t mapoff = (size_t)b * 4 * G.ny * G.nx;
@@ -357,10 +363,15 @@ __device__ __forceinline__ void fwd_band(const FwdArgs& a, const int b, const in
     }
 }
 
+// The map-averaging seed pass is held to 128 VGPRs (four waves per SIMD, as
+// the other map-averaging bodies; it needs 129 unconstrained, and spills
+// nothing at 128).
 template <int BULGE, int NDISC, int HALO, int MODE, int LW, int BO = 0>
-__global__ void __launch_bounds__(512) fwd_kernel(FwdArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MODE == MODE_FBAR && !LW ? 4 : 1)))
+fwd_kernel(FwdArgs a) {
     extern __shared__ __align__(16) float smem[];
-    fwd_band<BULGE, NDISC, HALO, MODE, LW, BO>(a, blockIdx.x / a.nbands, blockIdx.x % a.nbands, smem, true);
+    fwd_band<BULGE, NDISC, HALO, MODE, LW, BO, MODE == MODE_FBAR && LW>(a, blockIdx.x / a.nbands,
+                                                                         blockIdx.x % a.nbands, smem);
 }
 
 }  // namespace gk

@@ -55,7 +55,7 @@ constexpr int RS_CAP = 16;      // lattice rows per model phase
 constexpr int GSUB_CAP = 4;     // pixel-row steps per model phase
 
 struct Layout {                 // LDS carve-up, identical on host and device
-    int tab, rows, red, stage, prange, fin, total_bytes;
+    int rows, red, stage, prange, fin, tab, total_bytes;
 };
 
 __host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (band_h - 1) * s + 2 * pad + 1; }
@@ -63,8 +63,9 @@ __host__ __device__ inline int nfr_max(int band_h, int s, int pad) { return (ban
 __host__ __device__ inline int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
 
 // nfin: floats of the per-step exchange buffer of the luminosity-weighted
-// mode (0 otherwise)
-__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int band_h, int nfin) {
+// mode (0 otherwise); tab_lds: an LDS copy of the special-function tables,
+// last (the forward bodies that read it, see fwd_band)
+__host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int band_h, int nfin, bool tab_lds) {
     Layout L;
     int off = 0;                                   // in 4-byte words
     L.rows = off;       off += rows * 4 * xw;
@@ -73,10 +74,8 @@ __host__ __device__ inline Layout make_layout(int rows, int xw, int nfrm, int ba
     L.stage = off;      off += 2 * band_h + 32;    // row spans and stencil half-widths
     L.prange = off;     off += (nfrm + rows - 1) / rows + 1;   // per phase: first column | width << 16
     L.fin = off;        off += nfin;
-    // the tables last, at a launch-dependent offset: a table lookup is then one
-    // base add and four reads with immediate offsets
-    off = (off + 3) & ~3;
-    L.tab = off;        off += TAB_ALL;
+    if (tab_lds) off = (off + 3) & ~3;
+    L.tab = off;        off += tab_lds ? TAB_ALL : 0;
     L.total_bytes = 4 * off;
     return L;
 }
@@ -119,14 +118,18 @@ struct AdjLayout {              // LDS carve-up of the adjoint (4-byte words), h
     int tab, ring, S, vt, ht, red, span, aof, prange, total_bytes;
 };
 
+// tab_lds: the special-function tables get an LDS copy (the luminosity-
+// weighted body, which evaluates the model twice per lattice point and runs
+// faster so); the other bodies read the constant-memory tables through the
+// vector L1 cache, which leaves the LDS for more lattice rows per phase
 __host__ __device__ inline AdjLayout adj_layout(int band_h, int band_w, int s, int pad, int D, int rows, int nlev,
-                                                int rb, int KP) {
+                                                int rb, int KP, bool tab_lds) {
     // a band of band_h x band_w pixels owns at most band_h s + 2 pad + 1
     // lattice rows, reached by at most band_h + D + 1 pixel rows (and columns)
     const int nrf = band_h + D + 1, ncf = band_w + D + 1;
     AdjLayout L;
     int off = 0;
-    L.tab = off;  off += TAB_ALL;
+    L.tab = off;  off += tab_lds ? TAB_ALL : 0;
     off = (off + 3) & ~3;
     L.ring = off; off += rb * ncf * 4;                             // float4 [rb][frame columns]
     L.S = off;    off += rows * (ncf + 2 * D) * nlev * 4;          // float4 [rows][frame columns + 2D][nlev]

@@ -14,7 +14,9 @@ namespace gk {
 // the items by decreasing cost, so the dispatcher hands out the longest items
 // first and the short ones fill the tail.  (A persistent loop over an atomic
 // queue kept loop-invariant state live across items: 206 instead of 125 VGPRs,
-// half the occupancy, and slower overall.)
+// half the occupancy, and slower overall.)  The special-function tables are
+// copied to LDS: the registers cap the occupancy at four waves per SIMD, which
+// the small bands' LDS with the copy still allows.
 // ============================================================================
 typedef const __attribute__((address_space(4))) int* const_word_ptr;
 
@@ -33,7 +35,7 @@ __global__ void __launch_bounds__(MULTI_BS) multi_kernel(const FwdArgs* __restri
     switch (comp) {
 #define GK_MCASE(BU, ND, HA)                                                                   \
     case BU * 100 + ND * 10 + HA:                                                              \
-        fwd_band<BU, ND, HA, MODE_LOGL, LW>(a, row, band, smem, true);                          \
+        fwd_band<BU, ND, HA, MODE_LOGL, LW, 0, 1>(a, row, band, smem);                         \
         break;
         GK_MCASE(1, 0, 0) GK_MCASE(1, 0, 1) GK_MCASE(1, 0, 2)
         GK_MCASE(1, 1, 0) GK_MCASE(1, 1, 1) GK_MCASE(1, 1, 2)
