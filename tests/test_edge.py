@@ -1,7 +1,8 @@
 """GPU parity on degenerate and limiting inputs: one-pixel, one-row and
 one-column grids, the widest stencil this build accepts (3 sigma s = 25
-lattice points, lag D = 10), a single valid pixel, non-finite data entries,
-and PSFs beyond the limits (rejected at creation)."""
+lattice points, lag D = 10), grids with sides of 400 to 4096 pixels, a
+single valid pixel, non-finite data entries, and PSFs beyond the limits
+(rejected at creation)."""
 import sys
 import zlib
 
@@ -162,4 +163,45 @@ def test_tail_branches(gk, bulge):
         tol = LOGL_ATOL if k == 0 else bound(spec, data, err, t)
         assert abs(logl[k] - lo) <= tol, (k, logl[k], lo)
         check_grad(g[k], M.grad_complex_step(spec, data, err, t), f"tails[{k}]")
+    grid.close()
+
+
+LARGE = {
+    # sides past the 384 pixels that an earlier adjoint layout capped, and the
+    # 4096-pixel maximum in each direction (forward bands and adjoint blocks
+    # of the library's default shapes)
+    "wide_square": W.GridSpec(420, 400, 0.05, 1, 0.8, 1, 1, W.HALO_NFW),
+    "widest_row": W.GridSpec(4096, 2, 0.02, 1, 1.2, 2, 1, W.HALO_HERNQUIST),
+    "tallest_column": W.GridSpec(3, 4096, 0.02, 1, 1.0, 1, 1, W.HALO_NONE),
+}
+
+
+@pytest.mark.parametrize("name", list(LARGE))
+def test_large_sides(gk, name):
+    spec = LARGE[name]
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    truth = W.draw_thetas(spec, 1, rng)[0]
+    data, err = M.synthetic_data(spec, truth, np.ones((spec.ny, spec.nx), bool), rng)
+    thetas = np.vstack([truth[None], W.draw_thetas(spec, 1, rng)])
+    say(f"[edge] {name}: {spec.nx}x{spec.ny} s={spec.supersample} sigma={spec.psf_sigma_px:.4f}")
+    grid = gk.Grid(spec, max_batch=4)
+    grid.set_data(data, err)
+    say(f"[edge] {name}: launch shape {grid.launch_shape(2)}, adjoint shape {grid.adjoint_shape()}")
+    th = torch.tensor(thetas, device="cuda")
+    maps = grid.maps(th).cpu().numpy().astype(np.float64)
+    logl = grid.loglike(th).cpu().numpy()
+    _, g = grid.loglike_grad(th[:1])
+    g = g.cpu().numpy()
+    for k, t in enumerate(thetas):
+        F = M.psf_maps(spec, t)
+        ref = np.stack([F[0], F[1], F[2], 1.0 / F[3]])
+        for m in (0, 2, 3):
+            assert np.max(np.abs(maps[k, m] / ref[m] - 1.0)) < MAP_RTOL, (k, m)
+        assert np.max(np.abs(maps[k, 1] - ref[1])) <= MAP_RTOL * np.max(np.abs(ref[1])) + 1e-6
+        lo = M.loglike(spec, data, err, t)
+        # the truth row: LOGL_ATOL up to 4e4 residuals, beyond that the FP32
+        # random-walk bound (the 420 x 400 grid has 6.7e5)
+        tol = logl_tol(spec, data, err, t, "truth") if k == 0 else bound(spec, data, err, t)
+        assert abs(logl[k] - lo) <= tol, (k, logl[k], lo)
+    check_grad(g[0], M.grad_complex_step(spec, data, err, truth), f"{name}[0]")
     grid.close()
