@@ -309,7 +309,8 @@ static int set_adj_shape(gk_grid* g, int bh, int bw, int rows) {
 // of r lattice rows then fills the threads once), widest first, then the
 // tallest bands for which a vector still spans at least two bands (more
 // workgroups) and the grid at most MAX_BANDS_ADJ bands (on a 100 x 100 grid,
-// B = 4096, bands of 50 x 100 pixels take 0.94 of the time of 100 x 50).  A grid whose adjoint fits no shape keeps
+// B = 4096, a gradient with bands of 50 x 100 pixels takes 0.94 of the time
+// with 100 x 50).  A grid whose adjoint fits no shape keeps
 // adj_nbands = 0: its forward calls work and its gradient calls return
 // GK_EINVAL.
 static int default_adj_shape(gk_grid* g) {
