@@ -71,3 +71,19 @@ def test_adjoint_work_counts():
     assert bench.flops_adjoint_per_point(st) == 382 + 88 + 4 + 18
     lw = W.workload("lw").spec
     assert bench.flops_adjoint_per_point(lw) == 382 + 157 + 12 + 56 + 4 + 19
+
+
+def test_traffic_records_match_the_forward_sources():
+    """The committed HBM-traffic records (from the FETCH_SIZE / WRITE_SIZE
+    counters) are keyed to the forward kernel's sources: the bench line only
+    reports them while the hash still matches, so a record left behind by a
+    kernel change shows up here, and its byte count follows from its raw
+    counters and calibration scales."""
+    import json
+    for name in ("stress", "realistic"):
+        with open(os.path.join(ROOT, "profiles", f"traffic_{name}.json")) as f:
+            t = json.load(f)
+        assert t["source_hash"] == bench.source_hash(), f"traffic_{name}.json is stale: re-run the counters"
+        assert tuple(t["source_files"]) == tuple(bench.FWD_SOURCES)
+        got = t["fetch_size_kib_raw"] * 1024 * t["fetch_scale"] + t["write_size_kib_raw"] * 1024 * t["write_scale"]
+        assert abs(got - t["bytes_per_launch"]) <= 1e-3 * t["bytes_per_launch"]
